@@ -1,0 +1,208 @@
+"""Pins of the CPU models of the Contour algorithm (oracle/contour_model.py).
+
+The models replay Definition 3 / Algorithm 1 and the asynchronous variant of
+Section III-B.  They are pinned by closed forms derived by hand from
+Definition 3 (tests/golden/closed_forms.txt), by the final labels of the
+union-find and BFS oracles, and by the invariants of Section II-A.
+
+Hand derivations (increasing-id path 0-1-...-(n-1), synchronous):
+  order 1: the edge <j-1, j> gives L_u[j] = L[j-1]; from L[j] = j - k this is
+           j - k - 1, so L[j] = max(0, j - k) after k iterations and n - 1
+           iterations change something.
+  order 2: with L[j] = j - d, edge <j-1, j> has L^2[j-1] = j - 1 - 2d, so the
+           offset grows d -> 2d + 1, d_k = 2^k - 1 and ceil(log2 n) iterations
+           change something.
+  chase to root: iteration 1 sets L[j] = j - 1 (every vertex is a root, the
+           larger one is hooked); iteration 2 follows each chain to 0 and maps
+           every vertex to 0: 2 changing iterations for n >= 3.
+"""
+import itertools
+import os
+import random
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from oracle import contour_model as cm
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def closed_form_cases():
+    out = []
+    with open(os.path.join(GOLDEN, "closed_forms.txt")) as f:
+        for line in f:
+            if not line.strip() or line.startswith("#"):
+                continue
+            fam, n, order, changing = [p.strip() for p in line.split("|")]
+            out.append((fam, int(n), int(order), int(changing)))
+    return out
+
+
+def family(fam, n):
+    if fam == "path":
+        return np.arange(n - 1), np.arange(1, n)
+    if fam == "complete":
+        pairs = list(itertools.combinations(range(n), 2))
+        return np.array([p[0] for p in pairs]), np.array([p[1] for p in pairs])
+    raise ValueError(fam)
+
+
+@pytest.mark.parametrize("case", closed_form_cases(), ids=lambda c: "%s-n%d-h%d" % c[:3])
+def test_sync_closed_forms(case):
+    fam, n, order, changing = case
+    src, dst = family(fam, n)
+    labels, iters, chg, _ = cm.contour_sync(src, dst, n, order)
+    assert chg == changing
+    assert iters == changing + 1
+    assert np.all(labels == 0)
+
+
+def test_sync_path_order1_states_follow_closed_form():
+    n = 12
+    src, dst = family("path", n)
+    _, _, _, states = cm.contour_sync(src, dst, n, 1, record=True)
+    for k, L in enumerate(states, start=1):
+        assert np.array_equal(L, np.maximum(0, np.arange(n) - k))
+
+
+def test_sync_path_order2_states_follow_closed_form():
+    n = 40
+    src, dst = family("path", n)
+    _, _, _, states = cm.contour_sync(src, dst, n, 2, record=True)
+    for k, L in enumerate(states, start=1):
+        assert np.array_equal(L, np.maximum(0, np.arange(n) - (2 ** k - 1)))
+
+
+def all_graphs(n):
+    slots = list(itertools.combinations(range(n), 2))
+    for mask in range(1 << len(slots)):
+        yield [slots[i] for i in range(len(slots)) if mask >> i & 1]
+
+
+@pytest.mark.parametrize("order", [1, 2, 3, cm.FULL])
+def test_sync_exhaustive_n_le_5(order):
+    for n in range(1, 6):
+        for pairs in all_graphs(n):
+            src = np.array([p[1] for p in pairs], np.int64)
+            dst = np.array([p[0] for p in pairs], np.int64)
+            exp = oracle.bfs_labels(src, dst, n)
+            assert np.array_equal(cm.contour_sync(src, dst, n, order)[0], exp), (order, pairs)
+
+
+@pytest.mark.parametrize("name", ["C-1", "C-2", "C-m", "C-11mm", "C-1m1m", "C-full", "C-3"])
+def test_sync_and_async_schedules_reach_oracle_labels(name):
+    rng = random.Random(7)
+    for trial in range(25):
+        n = rng.randint(1, 60)
+        m = rng.randint(0, min(2 * n, n * (n - 1) // 2))
+        src, dst = graphgen.er(n, m, 100 + trial) if m else (np.zeros(0, np.int32),) * 2
+        exp = oracle.uf_labels(src, dst, n)
+        sched = cm.schedule(name)
+        assert np.array_equal(cm.contour_sync(src, dst, n, sched)[0], exp)
+        order = list(range(m))
+        rng.shuffle(order)
+        assert np.array_equal(cm.contour_async(src, dst, n, sched, order)[0], exp)
+
+
+def test_async_never_needs_more_sweeps_than_order1_on_paths():
+    # ordering of Section IV-C: iterations(C-m) <= iterations(C-2) <= iterations(C-1)
+    for n in (10, 33, 100):
+        src, dst = graphgen.grid_holes(1, n, 0.0, 1, permute_ids=True)
+        s1 = cm.contour_sync(src, dst, n, 1)[1]
+        s2 = cm.contour_sync(src, dst, n, 2)[1]
+        sm = cm.contour_sync(src, dst, n, 1024)[1]
+        assert sm <= s2 <= s1
+
+
+def test_order_m_equals_chase_to_root_when_chains_are_short():
+    src, dst = graphgen.er(200, 300, 3)
+    a = cm.contour_sync(src, dst, 200, 1024, record=True)[3]
+    b = cm.contour_sync(src, dst, 200, cm.FULL, record=True)[3]
+    assert len(a) == len(b) and all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_theorem_bound_holds_for_sync_order2_on_small_graphs():
+    # Graph Convergence theorem: at most ceil(log_{3/2} d_max) + 1 iterations
+    # (here counted as changing iterations); checked on paths and grids.
+    for n in (5, 17, 50, 200, 1000):
+        src, dst = graphgen.grid_holes(1, n, 0.0, 2, permute_ids=True)
+        chg = cm.contour_sync(src, dst, n, 2)[2]
+        assert chg <= cm.theorem_bound(n - 1)
+    for r, c in ((4, 4), (8, 8), (16, 16), (20, 30)):
+        src, dst = graphgen.grid_holes(r, c, 0.0, 2)
+        chg = cm.contour_sync(src, dst, r * c, 2)[2]
+        assert chg <= cm.theorem_bound(r + c - 2)
+
+
+def test_theorem_bound_values():
+    assert cm.theorem_bound(1) == 1
+    assert cm.theorem_bound(2) == 3          # ceil(1.709...) + 1
+    assert cm.theorem_bound(8190) == 24
+    assert cm.theorem_bound(11222) == 24     # 1.5**23 = 11222.7
+    assert cm.theorem_bound(11223) == 25
+
+
+def test_paper_check_equals_would_write_for_order2():
+    # For order 2 the early convergence test of Section III-B-2 holds exactly
+    # when the edge's conditional assignments would change something.
+    rng = random.Random(3)
+    for _ in range(3000):
+        n = rng.randint(1, 9)
+        # a random label array with L[x] <= x (a forest whose roots are minima)
+        L = [rng.randint(0, x) for x in range(n)]
+        w, v = rng.randrange(n), rng.randrange(n)
+        _, values, z = cm.mm_edge_reads(L, w, v, 2)
+        assert cm.paper_check(L, w, v) == any(val > z for val in values)
+
+
+def test_lost_update_model_reaches_oracle_labels():
+    rng = random.Random(5)
+    for trial in range(60):
+        n = rng.randint(2, 80)
+        m = rng.randint(1, min(3 * n, n * (n - 1) // 2))
+        src, dst = graphgen.er(n, m, 500 + trial)
+        exp = oracle.uf_labels(src, dst, n)
+        for order in (1, 2, 3, cm.FULL):
+            lab, sweeps, ok = cm.contour_lost_update(src, dst, n, order, group=8, seed=trial)
+            assert ok and np.array_equal(lab, exp), (trial, order)
+
+
+def test_async_warm_start_from_partial_state():
+    src, dst = graphgen.er(300, 400, 9)
+    exp = oracle.uf_labels(src, dst, 300)
+    _, _, _, states = cm.contour_sync(src, dst, 300, 2, record=True)
+    mid = states[0]
+    lab, _ = cm.contour_async(src, dst, 300, 2, L0=mid)
+    assert np.array_equal(lab, exp)
+
+
+def test_post_write_check_is_unsound():
+    # Reading the early convergence check after an edge's own writes (instead
+    # of on its pre-write reads) can stop before the fixed point; the model
+    # uses pre-write reads.  A search over small random graphs finds a case
+    # where the post-write reading ends with labels that differ from the oracle.
+    rng = random.Random(11)
+    found = False
+    for trial in range(400):
+        n = rng.randint(3, 10)
+        m = rng.randint(1, n * (n - 1) // 2)
+        src, dst = graphgen.er(n, m, 900 + trial)
+        L = list(range(n))
+        for _ in range(100):
+            active = False
+            for e in range(m):
+                targets, _, z = cm.mm_edge_reads(L, int(src[e]), int(dst[e]), 2)
+                for x in targets:
+                    if L[x] > z:
+                        L[x] = z
+                if cm.paper_check(L, int(src[e]), int(dst[e])):
+                    active = True
+            if not active:
+                break
+        if not np.array_equal(np.array(L, np.int32), oracle.uf_labels(src, dst, n)):
+            found = True
+            break
+    assert found
