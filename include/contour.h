@@ -1,0 +1,199 @@
+/*
+ * contour.h -- C ABI of libcontour, exact connected components on one
+ * MI355X (gfx950) by the Contour minimum-mapping algorithm
+ * (Du, Alvarado Rodriguez, Li, Dindoost, Bader, "Contour Algorithm for
+ * Connectivity", arXiv 2311.02811).
+ *
+ * What every entry point computes (Section II-A, Theorem "Graph Convergence"):
+ * for an undirected graph with vertex ids 0..n-1 and an edge list, the label
+ * of vertex v is the minimum vertex id of v's connected component.  The
+ * result is unique, so it is the same bit for bit for every operator order,
+ * write mode, schedule, launch geometry and edge order.
+ *
+ * How: labels start at L[i] = i (Algorithm 1, initialisation).  Each sweep
+ * applies the h-order minimum-mapping operator MM^h (Definition 3) to every
+ * edge <w, v>: z = min(L^h[w], L^h[v]) is written into L[x] for every x on
+ * the chains w, L[w], ..., L^{h-1}[w] and v, ..., L^{h-1}[v] whose value
+ * exceeds z (the conditional assignment of Definition 1).  By default the
+ * array is updated in place (asynchronous update, Section III-B-1) with plain
+ * stores (no atomics, Section III-B-3), and a sweep in which no edge finds
+ * anything to change ends the run (early convergence check, Section III-B-2,
+ * evaluated on the values each edge read before its own writes).
+ *
+ * Conventions shared by every entry point
+ *   * Arrays are device pointers owned by the caller unless stated.  Edge
+ *     arrays are int32 structure-of-arrays src[m], dst[m]; each undirected
+ *     edge appears once in either orientation; self-loops and duplicates are
+ *     allowed.  Label arrays must not alias the edge arrays.
+ *   * Calls are stream ordered: they enqueue work on `stream` (a hipStream_t,
+ *     NULL for the null stream) and return before it completes, except where
+ *     a driver mode says it blocks.  Results are valid once the stream has
+ *     completed the enqueued work.
+ *   * Argument errors (NULL with a non-zero size, negative sizes, bad
+ *     options) are returned synchronously and nothing is enqueued.
+ *   * Data errors are reported through contour_stats_t.status after the
+ *     stream completes: an edge with an id outside [0, n) is skipped, never
+ *     dereferenced, and status becomes CONTOUR_ERANGE (labels are then the
+ *     labels of the graph without those edges); running out of sweeps gives
+ *     CONTOUR_ENOCONV with a valid partial state that a warm start resumes.
+ *   * HIP runtime failures return CONTOUR_EHIP; contour_last_hip_error()
+ *     then gives the hipError_t of the calling thread's last failure.
+ *   * The library owns a small per-(device, stream) workspace (control
+ *     words); calls on different streams may run concurrently, calls on the
+ *     same stream are serialised by the stream.
+ */
+#ifndef CONTOUR_H
+#define CONTOUR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* contour_stream_t; /* a hipStream_t */
+
+typedef enum {
+    CONTOUR_OK = 0,
+    CONTOUR_EINVAL = 1,  /* bad argument or option */
+    CONTOUR_ERANGE = 2,  /* an edge id outside [0, n) (reported in stats) */
+    CONTOUR_ENOMEM = 3,  /* device allocation of the workspace failed */
+    CONTOUR_EHIP = 4,    /* a HIP runtime call failed */
+    CONTOUR_ENOCONV = 5, /* max_sweeps reached before convergence (stats) */
+    CONTOUR_ENOTSUP = 6  /* option combination not supported */
+} contour_status_t;
+
+/* Operator order h of MM^h (Definition 3).  1, 2 (default), 3, ... up to
+ * CONTOUR_ORDER_MAX are exact orders; CONTOUR_ORDER_FULL follows each chain
+ * to its root (L[x] = x) and writes z to every vertex on it, root included.
+ * Because every chain strictly decreases until its root, an order larger
+ * than the longest chain acts exactly like CONTOUR_ORDER_FULL. */
+#define CONTOUR_ORDER_FULL (-1)
+#define CONTOUR_ORDER_MAX 1024
+
+/* Operator schedules of Section III-B-4. */
+#define CONTOUR_SCHED_FIXED 0 /* `order` in every sweep (C-1, C-2, C-m) */
+#define CONTOUR_SCHED_11MM 1  /* order 1 for the first k1 sweeps, then `order` (C-11mm) */
+#define CONTOUR_SCHED_1M1M 2  /* order 1 and `order` alternately, from 1 (C-1m1m) */
+
+/* Write rule of the conditional assignment. */
+#define CONTOUR_WRITE_PLAIN 0  /* if (read > z) L[x] = z;  benign race, Section III-B-3 */
+#define CONTOUR_WRITE_ATOMIC 1 /* if (read > z) atomic_min(&L[x], z);  Eq. (cas) */
+
+/* Update rule. */
+#define CONTOUR_UPDATE_ASYNC 0 /* one array updated in place (Section III-B-1) */
+#define CONTOUR_UPDATE_SYNC 1  /* Algorithm 1 (C-Syn): read L, atomic-min into L_u, L = L_u */
+
+/* Driver: how sweeps are sequenced. */
+#define CONTOUR_DRIVER_PERSISTENT 0 /* one launch; workgroups pull edge chunks from a task
+                                       counter and open the next sweep on device */
+#define CONTOUR_DRIVER_HOSTLOOP 1   /* one launch per sweep; the host reads the convergence
+                                       word every few sweeps (this call blocks) */
+
+typedef struct {
+    int32_t order;       /* 0 = default (2); 1..CONTOUR_ORDER_MAX or CONTOUR_ORDER_FULL */
+    int32_t schedule;    /* CONTOUR_SCHED_* */
+    int32_t k1;          /* C-11mm: sweeps of order 1 before switching (0 = 2) */
+    int32_t write_mode;  /* CONTOUR_WRITE_* */
+    int32_t update;      /* CONTOUR_UPDATE_* (SYNC requires DRIVER_HOSTLOOP) */
+    int32_t driver;      /* CONTOUR_DRIVER_* */
+    int32_t max_sweeps;  /* 0 = no limit */
+    int32_t warm_start;  /* 1: labels_inout holds a state with L[x] <= x and L[x] in x's
+                            component (e.g. a partial result); 0: start from L[x] = x */
+    int32_t block;       /* threads per workgroup, 0 = auto (multiple of 64, <= 1024) */
+    int32_t edges_per_thread; /* 0 = auto; 1, 2, 4 or 8 */
+    int32_t chunk_tiles; /* persistent driver: tiles (block * edges_per_thread edges)
+                            per task, 0 = auto */
+    int32_t grid;        /* workgroups, 0 = auto (all resident) */
+} contour_opts_t;
+
+typedef struct {
+    int32_t status;             /* contour_status_t of the data checks */
+    int32_t sweeps_executed;    /* sweeps run, including the final one that changed nothing */
+    int32_t sweeps_with_writes; /* sweeps in which some edge changed a label */
+    int32_t reserved;
+} contour_stats_t;
+
+/* Fill *opts with the defaults (order 2, fixed schedule, plain writes,
+ * asynchronous update, persistent driver, no sweep limit, automatic geometry). */
+void contour_default_opts(contour_opts_t* opts);
+
+/* contour_cc: labels_out[v] = minimum vertex id of v's component.
+ *   src, dst    device int32[m], ids in [0, n)
+ *   m           edge count, >= 0 (0: labels are the identity)
+ *   n           vertex count, >= 0 (0: nothing is done)
+ *   labels_out  device int32[n], written
+ * Defaults of contour_default_opts; data errors are not reported (use
+ * contour_cc_ex for stats).  Returns CONTOUR_OK or a synchronous error. */
+int contour_cc(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
+               int32_t* labels_out, contour_stream_t stream);
+
+/* contour_cc_ex: as contour_cc with options and statistics.
+ *   labels_inout  device int32[n]; read first when opts->warm_start, then written
+ *   opts          NULL for defaults
+ *   stats         NULL, or a device (or host-pinned) contour_stats_t written by the
+ *                 device when the solve ends
+ * Returns CONTOUR_OK, CONTOUR_EINVAL, CONTOUR_ENOTSUP, CONTOUR_ENOMEM or CONTOUR_EHIP. */
+int contour_cc_ex(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
+                  int32_t* labels_inout, const contour_opts_t* opts, contour_stats_t* stats,
+                  contour_stream_t stream);
+
+/* ------------------------------------------------------------ batches -- */
+/* A CSR-of-graphs batch of G independent graphs.  Graph g owns local vertex
+ * ids 0..n_g-1 with n_g = vertex_offsets[g+1] - vertex_offsets[g] (< 2^31),
+ * and edges edge_offsets[g] .. edge_offsets[g+1] of src/dst, written in local
+ * ids.  Its labels (local minimum ids) land at labels_out + vertex_offsets[g].
+ * Each graph's labels are independent of the rest of the batch. */
+typedef struct {
+    int32_t num_graphs;
+    const int64_t* h_edge_offsets;   /* host int64[G+1], read at plan creation */
+    const int64_t* h_vertex_offsets; /* host int64[G+1], read at plan creation */
+    const int32_t* src;              /* device int32[edge_offsets[G]] */
+    const int32_t* dst;              /* device int32[edge_offsets[G]] */
+    int32_t* labels_out;             /* device int32[vertex_offsets[G]] */
+    contour_stats_t* stats_out;      /* device contour_stats_t[G], or NULL */
+} contour_batch_t;
+
+typedef struct contour_plan* contour_plan_t;
+
+/* Build a reusable plan: sorts the graphs into size classes (labels in LDS,
+ * one workgroup per graph with labels in global memory, several workgroups
+ * per graph), picks the per-class order and geometry (opts fields that are
+ * non-zero override the tuned choice), and allocates the plan's device
+ * tables.  The pointers in *batch are captured; the arrays they point to
+ * must stay valid for launches.  Returns CONTOUR_OK, CONTOUR_EINVAL,
+ * CONTOUR_ENOMEM or CONTOUR_EHIP. */
+int contour_batch_plan_create(const contour_batch_t* batch, const contour_opts_t* opts,
+                              contour_plan_t* plan_out);
+
+/* Enqueue one solve of every graph of the plan on `stream`.  Enqueues only
+ * kernels (no allocation, no host synchronisation, no memset), so it can be
+ * captured into a hipGraph and replayed.  Returns CONTOUR_OK or CONTOUR_EHIP. */
+int contour_batch_plan_launch(contour_plan_t plan, contour_stream_t stream);
+
+/* Release a plan and its device tables (waits for the device). */
+int contour_batch_plan_destroy(contour_plan_t plan);
+
+/* Create, launch and destroy a plan in one call (blocks until done). */
+int contour_cc_batched(const contour_batch_t* batch, const contour_opts_t* opts,
+                       contour_stream_t stream);
+
+/* ------------------------------------------------------- profiling ---- */
+/* Optional timing hook for benchmarks.  When set (non-NULL hipEvent_t
+ * handles), contour_cc / contour_cc_ex record `begin` on the call's stream
+ * just before the first sweep kernel and `end` just after the last, so the
+ * pair brackets exactly the sweep kernels (label initialisation and the
+ * statistics write excluded).  The setting is per calling thread; pass NULL
+ * twice to clear it.  The events are owned by the caller. */
+void contour_set_timing_events(void* begin, void* end);
+
+/* ------------------------------------------------------------- misc ---- */
+const char* contour_status_string(int status);
+int contour_last_hip_error(void);
+const char* contour_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CONTOUR_H */

@@ -1,0 +1,133 @@
+"""Exact connected components on MI355X by the Contour minimum-mapping algorithm.
+
+Python binding of libcontour.so (C ABI in include/contour.h).  PyTorch only
+supplies device memory and streams; every step of the solve runs in the HIP
+library, and there is no CPU fallback.
+
+    labels = cc(src, dst, n)            # src, dst: int32 CUDA tensors
+    labels[v] == min vertex id of v's component
+
+Operator orders, schedules, write modes and drivers follow Definition 3,
+Algorithm 1 and Section III-B of the paper (arXiv 2311.02811).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+from ._lib import ContourOpts, load, lib_path  # noqa: F401
+
+ORDER_FULL = -1
+_SCHED = {"fixed": 0, "11mm": 1, "1m1m": 2}
+_WRITE = {"plain": 0, "atomic": 1}
+_UPDATE = {"async": 0, "sync": 1}
+_DRIVER = {"persistent": 0, "hostloop": 1}
+
+OK, EINVAL, ERANGE, ENOMEM, EHIP, ENOCONV, ENOTSUP = range(7)
+
+
+class ContourError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        lib = load()
+        msg = lib.contour_status_string(code).decode()
+        if code == EHIP:
+            msg += " (hipError %d)" % lib.contour_last_hip_error()
+        super().__init__("%s: %s" % (what, msg))
+        self.code = code
+
+
+@dataclass
+class Stats:
+    status: int
+    sweeps_executed: int
+    sweeps_with_writes: int
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_edges(src, dst):
+    torch = _torch()
+    for name, t in (("src", src), ("dst", dst)):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.int32 or not t.is_cuda:
+            raise TypeError("%s must be an int32 CUDA tensor" % name)
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+    if src.shape != dst.shape or src.dim() != 1:
+        raise ValueError("src and dst must be 1-D of equal length")
+    if src.device != dst.device:
+        raise ValueError("src and dst are on different devices")
+
+
+def make_opts(order=2, schedule="fixed", k1=2, write="plain", update="async",
+              driver="persistent", max_sweeps=0, warm_start=False, block=0,
+              edges_per_thread=0, chunk_tiles=0, grid=0) -> ContourOpts:
+    o = ContourOpts()
+    load().contour_default_opts(ctypes.byref(o))
+    o.order = ORDER_FULL if order in ("full", ORDER_FULL) else int(order)
+    o.schedule = _SCHED[schedule]
+    o.k1 = int(k1)
+    o.write_mode = _WRITE[write]
+    o.update = _UPDATE[update]
+    o.driver = _DRIVER[driver]
+    o.max_sweeps = int(max_sweeps)
+    o.warm_start = 1 if warm_start else 0
+    o.block = int(block)
+    o.edges_per_thread = int(edges_per_thread)
+    o.chunk_tiles = int(chunk_tiles)
+    o.grid = int(grid)
+    return o
+
+
+def cc(src, dst, n: int, labels=None, stream=None):
+    """labels[v] = minimum vertex id of v's component (defaults: order 2,
+    asynchronous update, plain stores, persistent driver)."""
+    torch = _torch()
+    _check_edges(src, dst)
+    if labels is None:
+        labels = torch.empty(max(int(n), 0), dtype=torch.int32, device=src.device)
+    rc = load().contour_cc(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                           src.numel(), int(n), ctypes.c_void_p(labels.data_ptr()),
+                           _stream_ptr(stream))
+    if rc != OK:
+        raise ContourError(rc, "contour_cc")
+    return labels
+
+
+def cc_ex(src, dst, n: int, labels=None, stream=None, stats: bool = True, **opts):
+    """contour_cc_ex with keyword options (see make_opts).  Returns
+    (labels, stats_tensor) where stats_tensor is a device int32[4]
+    (status, sweeps_executed, sweeps_with_writes, 0); read_stats() converts it."""
+    torch = _torch()
+    _check_edges(src, dst)
+    if labels is None:
+        labels = torch.empty(max(int(n), 0), dtype=torch.int32, device=src.device)
+    elif labels.dtype != torch.int32 or not labels.is_cuda or labels.numel() != n:
+        raise ValueError("labels must be an int32 CUDA tensor of n elements")
+    o = make_opts(**opts)
+    st = torch.zeros(4, dtype=torch.int32, device=src.device) if stats else None
+    rc = load().contour_cc_ex(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                              src.numel(), int(n), ctypes.c_void_p(labels.data_ptr()),
+                              ctypes.byref(o), ctypes.c_void_p(st.data_ptr() if stats else 0),
+                              _stream_ptr(stream))
+    if rc != OK:
+        raise ContourError(rc, "contour_cc_ex")
+    return labels, st
+
+
+def read_stats(st) -> Stats:
+    v = st.tolist()
+    return Stats(v[0], v[1], v[2])
+
+
+def version() -> str:
+    return load().contour_version().decode()

@@ -1,0 +1,328 @@
+// contour_device.hpp -- device-side building blocks of the Contour sweep.
+//
+// One edge <w, v> under the h-order minimum-mapping operator MM^h
+// (Definition 3): read the chains x_0 = w, x_1 = L[x_0], ..., x_h and
+// y_0 = v, ..., y_h, take z = min(x_h, y_h), and for i < h store z into
+// L[x_i] (resp. L[y_i]) when the value read there, x_{i+1}, exceeds z
+// (conditional assignment, Definition 1).  A chain stops early at a root
+// (L[x] = x): deeper levels would only repeat it.
+//
+// Every label array the kernels touch satisfies L[x] <= x at every instant
+// (it holds initially, and a store only ever lowers a value it read to a
+// smaller label of the same component), so each chain is non-increasing and
+// the edge changes something exactly when max(x_1, y_1) > z.  That is the
+// early convergence test of Section III-B-2 (for h >= 2 it is the paper's
+// L[v] != L^2[v] || L[w] != L^2[w] || L[v] != L[w]), and it is evaluated on
+// the values read before the edge's own stores.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace contour {
+
+// Per-solve control block (one per graph in a batch), 64 bytes.
+struct Ctl {
+    unsigned long long next_task;  // persistent driver: next task index to hand out
+    unsigned long long done_task;  // persistent driver: tasks completed
+    int last_change;               // 1 + index of the last sweep in which an edge changed a label
+    int state;                     // 0 running, 1 converged, 2 sweep limit, 3 bad warm start
+    int range_err;                 // an edge had an id outside [0, n)
+    int sweeps;                    // sweeps executed (set when the solve ends)
+    int joined;                    // batched multi-workgroup graphs: workgroups that joined
+    int pad[3];
+    unsigned long long t0;         // wall clock at the start of the solve (watchdog)
+    unsigned long long pad2;
+};
+static_assert(sizeof(Ctl) == 64, "control block is one 64-byte line");
+
+enum { ST_RUNNING = 0, ST_CONVERGED = 1, ST_LIMIT = 2, ST_BAD_START = 3, ST_TIMEOUT = 4 };
+
+// Watchdog: a solve that runs longer than its time budget (measured with the
+// constant-rate wall clock) stops as if it had hit the sweep limit, so no
+// kernel can spin forever whatever the input.
+__device__ __forceinline__ bool watchdog_expired(const Ctl* c, unsigned long long budget)
+{
+    return budget != 0 && wall_clock64() - c->t0 > budget;
+}
+
+// Operator schedule (Section III-B-4): order of MM^h used in a given sweep.
+struct Sched {
+    int order;  // 1..1024, or -1 for chase-to-root
+    int kind;   // 0 fixed, 1 C-11mm, 2 C-1m1m
+    int k1;     // C-11mm: sweeps of order 1 first
+};
+
+__device__ __forceinline__ int order_of_sweep(const Sched& s, int sweep)
+{
+    if (s.kind == 1) return sweep < s.k1 ? 1 : s.order;
+    if (s.kind == 2) return (sweep & 1) ? s.order : 1;
+    return s.order;
+}
+
+// Edge ids are streamed once per sweep: non-temporal loads keep them from
+// displacing the label array in the caches.
+__device__ __forceinline__ int ld_edge(const int* p) { return __builtin_nontemporal_load(p); }
+
+template <bool ATOMIC>
+__device__ __forceinline__ void put(int* L, int x, int z)
+{
+    if (ATOMIC)
+        __hip_atomic_fetch_min(L + x, z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        L[x] = z;
+}
+
+// ---------------------------------------------------------------------------
+// Edge tile: BLOCK * EPT consecutive edges starting at `base`; thread t owns
+// edges base + k * BLOCK + t (k < EPT), so every load instruction of a wave
+// reads 256 contiguous bytes.  All first-level gathers of a thread are issued
+// before any second-level gather, and all gathers before any store.
+// R is the array read, W the array written; they are the same array for the
+// asynchronous update and differ for the synchronous one (Algorithm 1).
+// Returns whether any of the thread's edges changed something; sets *rerr
+// when an edge id is outside [0, n) (that edge is skipped).
+// ---------------------------------------------------------------------------
+
+template <int EPT, int BLOCK>
+__device__ __forceinline__ void load_tile(const int* __restrict__ src, const int* __restrict__ dst,
+                                          long long base, long long m, unsigned n, int (&w)[EPT],
+                                          int (&v)[EPT], bool (&ok)[EPT], int& rerr)
+{
+    // Loads are unconditional (an edge past the end re-reads edge m-1, an
+    // invalid edge gathers label 0) so that every load of the tile is in
+    // flight at once instead of each waiting behind a branch.
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const long long e = base + (long long)k * BLOCK + threadIdx.x;
+        ok[k] = e < m;
+        const long long ec = ok[k] ? e : m - 1;
+        w[k] = ld_edge(src + ec);
+        v[k] = ld_edge(dst + ec);
+    }
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const bool inr = (unsigned)w[k] < n && (unsigned)v[k] < n;
+        if (ok[k] && !inr) rerr = 1;
+        ok[k] = ok[k] && inr;
+        w[k] = ok[k] ? w[k] : 0;
+        v[k] = ok[k] ? v[k] : 0;
+    }
+}
+
+// MM^1: z = min(L[w], L[v]); targets w, v.
+template <int EPT, bool ATOMIC>
+__device__ __forceinline__ bool tile_order1(const int* R, int* W, const int (&w)[EPT],
+                                            const int (&v)[EPT], const bool (&ok)[EPT])
+{
+    int a[EPT], b[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        a[k] = R[w[k]];
+        b[k] = R[v[k]];
+    }
+    bool pred = false;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int z = min(a[k], b[k]);
+        const bool act = ok[k] && max(a[k], b[k]) > z;
+        pred |= act;
+        if (act && a[k] > z) put<ATOMIC>(W, w[k], z);
+        if (act && b[k] > z) put<ATOMIC>(W, v[k], z);
+    }
+    return pred;
+}
+
+// MM^2: z = min(L[L[w]], L[L[v]]); targets w, v, L[w], L[v].
+template <int EPT, bool ATOMIC>
+__device__ __forceinline__ bool tile_order2(const int* R, int* W, const int (&w)[EPT],
+                                            const int (&v)[EPT], const bool (&ok)[EPT])
+{
+    int a[EPT], b[EPT], a2[EPT], b2[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        a[k] = R[w[k]];
+        b[k] = R[v[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        a2[k] = R[a[k]];
+        b2[k] = R[b[k]];
+    }
+    bool pred = false;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int z = min(a2[k], b2[k]);
+        const bool act = ok[k] && max(a[k], b[k]) > z;
+        pred |= act;
+        if (act && a[k] > z) put<ATOMIC>(W, w[k], z);
+        if (act && a2[k] > z) put<ATOMIC>(W, a[k], z);
+        if (act && b[k] > z) put<ATOMIC>(W, v[k], z);
+        if (act && b2[k] > z) put<ATOMIC>(W, b[k], z);
+    }
+    return pred;
+}
+
+// MM^3: z = min(L^3[w], L^3[v]); targets w, L[w], L^2[w] and the same for v.
+template <int EPT, bool ATOMIC>
+__device__ __forceinline__ bool tile_order3(const int* R, int* W, const int (&w)[EPT],
+                                            const int (&v)[EPT], const bool (&ok)[EPT])
+{
+    int a[EPT], b[EPT], a2[EPT], b2[EPT], a3[EPT], b3[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        a[k] = R[w[k]];
+        b[k] = R[v[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        a2[k] = R[a[k]];
+        b2[k] = R[b[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        a3[k] = R[a2[k]];
+        b3[k] = R[b2[k]];
+    }
+    bool pred = false;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int z = min(a3[k], b3[k]);
+        const bool act = ok[k] && max(a[k], b[k]) > z;
+        pred |= act;
+        if (act && a[k] > z) put<ATOMIC>(W, w[k], z);
+        if (act && a2[k] > z) put<ATOMIC>(W, a[k], z);
+        if (act && a3[k] > z) put<ATOMIC>(W, a2[k], z);
+        if (act && b[k] > z) put<ATOMIC>(W, v[k], z);
+        if (act && b2[k] > z) put<ATOMIC>(W, b[k], z);
+        if (act && b3[k] > z) put<ATOMIC>(W, b2[k], z);
+    }
+    return pred;
+}
+
+// MM^h for any h >= 1 (h < 0: chase to the root).  First walk: read both
+// chains level by level (all of a thread's edges advance together) until
+// level h or the root.  Second walk, only for edges that change something:
+// from each endpoint again, store z where the value read exceeds z, stopping
+// at level h, at the root, or where the value read is already <= z (the rest
+// of a non-increasing chain is then <= z too).  The second walk re-reads the
+// chain; any value it reads is a valid label, and if its reads differ from
+// the first walk's, some other edge stored in this sweep, so a sweep that
+// reports a change always makes one.
+template <int EPT, bool ATOMIC>
+__device__ __forceinline__ bool tile_orderh(const int* R, int* W, const int (&w)[EPT],
+                                            const int (&v)[EPT], const bool (&ok)[EPT], int h)
+{
+    int cw[EPT], cv[EPT], fw[EPT], fv[EPT];
+    bool dw[EPT], dv[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        cw[k] = w[k];
+        cv[k] = v[k];
+        fw[k] = w[k];
+        fv[k] = v[k];
+        dw[k] = !ok[k];
+        dv[k] = !ok[k];
+    }
+    for (int lvl = 0; h < 0 || lvl < h; ++lvl) {
+        bool more = false;
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            int nw = cw[k], nv = cv[k];
+            if (!dw[k]) nw = R[cw[k]];
+            if (!dv[k]) nv = R[cv[k]];
+            if (lvl == 0) {
+                fw[k] = nw;
+                fv[k] = nv;
+            }
+            if (!dw[k]) {
+                if (nw == cw[k]) dw[k] = true;
+                cw[k] = nw;
+            }
+            if (!dv[k]) {
+                if (nv == cv[k]) dv[k] = true;
+                cv[k] = nv;
+            }
+            more |= !dw[k] || !dv[k];
+        }
+        if (!more) break;
+    }
+    bool pred = false;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        if (!ok[k]) continue;
+        int z = min(cw[k], cv[k]);
+        if (max(fw[k], fv[k]) <= z) continue;
+        pred = true;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            int x = side ? v[k] : w[k];
+            for (int lvl = 0; h < 0 || lvl < h; ++lvl) {
+                int val = R[x];
+                if (val > z) put<ATOMIC>(W, x, z);
+                if (val <= z || val == x) break;
+                x = val;
+            }
+        }
+    }
+    return pred;
+}
+
+// Apply MM^ORDER (ORDER 0: the run-time order h) to the tiles
+// [first, first + count) of the edge list, stopping at m.
+template <int ORDER, int EPT, int BLOCK, bool ATOMIC>
+__device__ __forceinline__ bool run_tiles(const int* __restrict__ src, const int* __restrict__ dst,
+                                          const int* R, int* W, long long first, long long count,
+                                          long long stride, long long m, unsigned n, int h, int& rerr)
+{
+    const long long tile_edges = (long long)BLOCK * EPT;
+    bool pred = false;
+    for (long long i = 0; i < count; ++i) {
+        const long long base = (first + i * stride) * tile_edges;
+        if (base >= m) break;
+        int w[EPT], v[EPT];
+        bool ok[EPT];
+        load_tile<EPT, BLOCK>(src, dst, base, m, n, w, v, ok, rerr);
+        if (ORDER == 1) pred |= tile_order1<EPT, ATOMIC>(R, W, w, v, ok);
+        else if (ORDER == 2) pred |= tile_order2<EPT, ATOMIC>(R, W, w, v, ok);
+        else if (ORDER == 3) pred |= tile_order3<EPT, ATOMIC>(R, W, w, v, ok);
+        else pred |= tile_orderh<EPT, ATOMIC>(R, W, w, v, ok, h);
+    }
+    return pred;
+}
+
+// Tiles first, first + stride, ... (count of them) under the order h.
+template <int EPT, int BLOCK, bool ATOMIC>
+__device__ __forceinline__ bool run_tiles_order(const int* __restrict__ src, const int* __restrict__ dst,
+                                                const int* R, int* W, long long first, long long count,
+                                                long long stride, long long m, unsigned n, int h,
+                                                int& rerr)
+{
+    switch (h) {
+    case 1: return run_tiles<1, EPT, BLOCK, ATOMIC>(src, dst, R, W, first, count, stride, m, n, h, rerr);
+    case 2: return run_tiles<2, EPT, BLOCK, ATOMIC>(src, dst, R, W, first, count, stride, m, n, h, rerr);
+    case 3: return run_tiles<3, EPT, BLOCK, ATOMIC>(src, dst, R, W, first, count, stride, m, n, h, rerr);
+    default:
+        // A chain strictly decreases until its root, so it has at most n
+        // vertices: chase-to-root is the order n operator, and the bound also
+        // caps every walk.
+        if (h < 0 || (unsigned)h > n) h = (int)n;
+        return run_tiles<0, EPT, BLOCK, ATOMIC>(src, dst, R, W, first, count, stride, m, n, h, rerr);
+    }
+}
+
+// Wait until every store this thread issued has completed, so a barrier that
+// follows publishes them to the rest of the workgroup's release.
+__device__ __forceinline__ void drain_stores() { __builtin_amdgcn_s_waitcnt(0); }
+
+__device__ __forceinline__ unsigned long long ld_acquire(const unsigned long long* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int ld_acquire(const int* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace contour

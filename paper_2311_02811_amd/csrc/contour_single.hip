@@ -1,0 +1,379 @@
+// contour_single.hip -- single-graph solve: label initialisation, the sweep
+// drivers (persistent on-device sequencing and host-sequenced sweeps), the
+// synchronous C-Syn variant, and the contour_cc / contour_cc_ex entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "contour.h"
+#include "contour_device.hpp"
+#include "contour_runtime.hpp"
+
+namespace contour {
+
+struct SolveArgs {
+    const int* src;
+    const int* dst;
+    int* L;
+    long long m;
+    unsigned n;
+    long long tasks;     // persistent driver: tasks per sweep
+    int tiles_per_task;  // persistent driver
+    Sched sched;
+    int max_sweeps;      // 0 = no limit
+    Ctl* ctl;
+    unsigned long long watchdog;  // wall-clock ticks a solve may run, 0 = unbounded
+};
+
+// ------------------------------------------------------------ set-up ----
+
+__global__ void k_reset_ctl(Ctl* c)
+{
+    int* p = reinterpret_cast<int*>(c);
+    if (threadIdx.x < sizeof(Ctl) / sizeof(int)) p[threadIdx.x] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) c->t0 = wall_clock64();
+}
+
+// Algorithm 1, initialisation: L[i] = i.  For a warm start, check instead that
+// every label satisfies 0 <= L[i] <= i, which keeps every chain the sweeps
+// follow inside [0, n); a violation stops the solve before any sweep.
+__global__ void k_init_labels(int* L, unsigned n, int warm, Ctl* c)
+{
+    bool bad = false;
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        if (!warm)
+            L[i] = (int)i;
+        else {
+            int x = L[i];
+            bad |= x < 0 || (unsigned)x > i;
+        }
+    }
+    if (bad) __hip_atomic_store(&c->state, (int)ST_BAD_START, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_write_stats(const Ctl* c, contour_stats_t* out, int range_err)
+{
+    if (threadIdx.x != 0) return;
+    int status = CONTOUR_OK;
+    if (c->state == ST_BAD_START)
+        status = CONTOUR_EINVAL;
+    else if (c->range_err || range_err)
+        status = CONTOUR_ERANGE;
+    else if (c->state == ST_LIMIT || c->state == ST_TIMEOUT)
+        status = CONTOUR_ENOCONV;
+    out->status = status;
+    out->sweeps_executed = c->sweeps;
+    out->sweeps_with_writes = c->last_change;
+    out->reserved = 0;
+}
+
+// ------------------------------------------------- persistent driver ----
+// One launch for the whole solve.  Task t covers edge chunk t % T of sweep
+// t / T (T tasks per sweep).  A workgroup takes the next task from a counter;
+// before working on sweep s it waits until all T tasks of sweep s-1 are done,
+// and if sweep s-1 changed nothing the solve has converged.  A workgroup only
+// ever waits for tasks that running workgroups have already taken, so the
+// scheme needs no co-residency and cannot deadlock.  Task completion is a
+// release (label stores drained, then an agent-scope release add), and the
+// wait is an acquire, so sweep s reads every store of sweeps < s.
+template <int EPT, int BLOCK, bool ATOMIC>
+__global__ __launch_bounds__(BLOCK) void k_persistent(SolveArgs a)
+{
+    __shared__ long long s_task;
+    __shared__ int s_go;
+    Ctl* c = a.ctl;
+    const long long tile_edges = (long long)BLOCK * EPT;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int go = 0;
+            long long t = 0;
+            if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ST_RUNNING) {
+                t = (long long)__hip_atomic_fetch_add(&c->next_task, 1ULL, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                long long sweep = t / a.tasks;
+                if (sweep > 0) {
+                    const unsigned long long need = (unsigned long long)(sweep * a.tasks);
+                    while (__hip_atomic_load(&c->done_task, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                        if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ST_RUNNING)
+                            break;
+                        if (watchdog_expired(c, a.watchdog)) {
+                            int expect = ST_RUNNING;
+                            __hip_atomic_compare_exchange_strong(&c->state, &expect, (int)ST_TIMEOUT,
+                                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ST_RUNNING) {
+                    int lc = __hip_atomic_load(&c->last_change, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    int st = ST_RUNNING;
+                    if (sweep > 0 && lc <= sweep - 1)
+                        st = ST_CONVERGED;
+                    else if (a.max_sweeps > 0 && sweep >= a.max_sweeps)
+                        st = ST_LIMIT;
+                    else if (watchdog_expired(c, a.watchdog))
+                        st = ST_TIMEOUT;
+                    if (st == ST_RUNNING) {
+                        go = 1;
+                    } else {
+                        int expect = ST_RUNNING;
+                        if (__hip_atomic_compare_exchange_strong(&c->state, &expect, st, __ATOMIC_RELAXED,
+                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                            __hip_atomic_store(&c->sweeps, (int)sweep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+            }
+            s_go = go;
+            s_task = t;
+        }
+        __syncthreads();
+        if (!s_go) break;
+        const long long t = s_task;
+        const long long sweep = t / a.tasks;
+        const long long chunk = t - sweep * a.tasks;
+        const int order = order_of_sweep(a.sched, (int)sweep);
+        bool pred = false;
+        int rerr = 0;
+        pred = run_tiles_order<EPT, BLOCK, ATOMIC>(a.src, a.dst, a.L, a.L, chunk * a.tiles_per_task,
+                                                   a.tiles_per_task, 1, a.m, a.n, order, rerr);
+        drain_stores();
+        const int any = __syncthreads_or(pred ? 1 : 0);
+        const int anyerr = __syncthreads_or(rerr);
+        if (threadIdx.x == 0) {
+            if (any)
+                __hip_atomic_fetch_max(&c->last_change, (int)sweep + 1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            if (anyerr) __hip_atomic_store(&c->range_err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&c->done_task, 1ULL, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// ------------------------------------------------- host-loop driver -----
+// One launch per sweep; kernel boundaries order the sweeps.  Sweep s first
+// looks at what sweep s-1 recorded: if it changed nothing (or the sweep limit
+// is reached, or the solve already ended) the kernel returns at once, so the
+// host may enqueue several sweeps ahead and only check every few.
+// R is read, W written: the same array for the asynchronous update; for the
+// synchronous update (Algorithm 1) W = L_u was filled with a copy of R first.
+template <int EPT, int BLOCK, bool ATOMIC>
+__global__ __launch_bounds__(BLOCK) void k_sweep(SolveArgs a, const int* R, int* W, int sweep)
+{
+    Ctl* c = a.ctl;
+    if (c->state != ST_RUNNING) return;
+    int st = ST_RUNNING;
+    if (sweep > 0 && c->last_change <= sweep - 1)
+        st = ST_CONVERGED;
+    else if (a.max_sweeps > 0 && sweep >= a.max_sweeps)
+        st = ST_LIMIT;
+    else if (watchdog_expired(c, a.watchdog))
+        st = ST_TIMEOUT;
+    if (st != ST_RUNNING) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            c->state = st;
+            c->sweeps = sweep;
+        }
+        return;
+    }
+    const int order = order_of_sweep(a.sched, sweep);
+    const long long tile_edges = (long long)BLOCK * EPT;
+    const long long ntiles = (a.m + tile_edges - 1) / tile_edges;
+    bool pred = false;
+    int rerr = 0;
+    const long long mine = blockIdx.x < ntiles ? (ntiles - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
+    pred = run_tiles_order<EPT, BLOCK, ATOMIC>(a.src, a.dst, R, W, blockIdx.x, mine, gridDim.x, a.m, a.n,
+                                               order, rerr);
+    const int any = __syncthreads_or(pred ? 1 : 0);
+    const int anyerr = __syncthreads_or(rerr);
+    if (threadIdx.x == 0) {
+        if (any) c->last_change = sweep + 1;
+        if (anyerr) c->range_err = 1;
+    }
+}
+
+// Synchronous update: L_u = L before the sweep (skipped once the solve ended).
+__global__ void k_copy_labels(const int* R, int* W, unsigned n, const Ctl* c)
+{
+    if (c->state != ST_RUNNING) return;
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) W[i] = R[i];
+}
+
+// ----------------------------------------------------- dispatch ---------
+
+typedef void (*persistent_fn)(SolveArgs);
+typedef void (*sweep_fn)(SolveArgs, const int*, int*, int);
+
+template <int BLOCK, bool ATOMIC>
+static void pick(int ept, persistent_fn* p, sweep_fn* s)
+{
+    switch (ept) {
+    case 1: *p = k_persistent<1, BLOCK, ATOMIC>; *s = k_sweep<1, BLOCK, ATOMIC>; break;
+    case 2: *p = k_persistent<2, BLOCK, ATOMIC>; *s = k_sweep<2, BLOCK, ATOMIC>; break;
+    case 4: *p = k_persistent<4, BLOCK, ATOMIC>; *s = k_sweep<4, BLOCK, ATOMIC>; break;
+    default: *p = k_persistent<8, BLOCK, ATOMIC>; *s = k_sweep<8, BLOCK, ATOMIC>; break;
+    }
+}
+
+static void pick_kernels(int block, int ept, bool atomic, persistent_fn* p, sweep_fn* s)
+{
+    if (block == 512) {
+        if (atomic) pick<512, true>(ept, p, s);
+        else pick<512, false>(ept, p, s);
+    } else {
+        if (atomic) pick<256, true>(ept, p, s);
+        else pick<256, false>(ept, p, s);
+    }
+}
+
+// Geometry: 256-thread workgroups; edges per thread grow with m so that small
+// graphs still spread over many workgroups and large ones get memory-level
+// parallelism; persistent tasks aim at several tasks per workgroup and sweep.
+static void auto_geometry(const DeviceInfo& d, long long m, Resolved* r)
+{
+    if (r->block == 0) r->block = 256;
+    if (r->ept == 0) {
+        long long threads_full = (long long)d.cus * 2048;  // one edge per resident thread
+        r->ept = m <= threads_full ? 1 : (m <= 4 * threads_full ? 2 : 4);
+    }
+}
+
+static int run_solve(const int* src, const int* dst, long long m, int n, int* L, const Resolved& r0,
+                     contour_stats_t* stats, hipStream_t stream)
+{
+    DeviceInfo d;
+    int rc = device_info(&d);
+    if (rc) return rc;
+    Workspace* ws = nullptr;
+    rc = workspace_for(stream, &ws);
+    if (rc) return rc;
+    Resolved r = r0;
+    auto_geometry(d, m, &r);
+
+    hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, stream, ws->ctl);
+    {
+        int blocks = (int)std::min<long long>(((long long)n + 255) / 256, (long long)d.cus * 8);
+        hipLaunchKernelGGL(k_init_labels, dim3(std::max(blocks, 1)), dim3(256), 0, stream, L,
+                           (unsigned)n, r.warm ? 1 : 0, ws->ctl);
+    }
+    CONTOUR_HIP(hipGetLastError());
+
+    hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+    timing_events(&ev_begin, &ev_end);
+    if (ev_begin) CONTOUR_HIP(hipEventRecord(ev_begin, stream));
+    if (m > 0) {
+        persistent_fn kp;
+        sweep_fn ks;
+        pick_kernels(r.block, r.ept, r.atomic || r.sync, &kp, &ks);
+        SolveArgs a;
+        a.src = src;
+        a.dst = dst;
+        a.L = L;
+        a.m = m;
+        a.n = (unsigned)n;
+        a.sched = r.sched;
+        a.max_sweeps = r.max_sweeps;
+        a.ctl = ws->ctl;
+        a.watchdog = watchdog_ticks(d);
+        const long long tile_edges = (long long)r.block * r.ept;
+        const long long ntiles = (m + tile_edges - 1) / tile_edges;
+        if (r.driver == CONTOUR_DRIVER_PERSISTENT) {
+            int occ = 0;
+            CONTOUR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kp, r.block, 0));
+            long long resident = (long long)std::max(occ, 1) * d.cus;
+            int tpt = r.chunk_tiles;
+            if (tpt == 0) {
+                // about 4 tasks per resident workgroup and sweep, at most 16 tiles each
+                tpt = (int)std::max<long long>(1, std::min<long long>(16, ntiles / (4 * resident)));
+            }
+            a.tiles_per_task = tpt;
+            a.tasks = (ntiles + tpt - 1) / tpt;
+            long long grid = r.grid ? r.grid : std::min<long long>(resident, a.tasks);
+            a.L = L;
+            hipLaunchKernelGGL(kp, dim3((unsigned)grid), dim3(r.block), 0, stream, a);
+            CONTOUR_HIP(hipGetLastError());
+        } else {
+            a.tiles_per_task = 1;
+            a.tasks = ntiles;
+            long long grid = r.grid ? r.grid : std::min<long long>(ntiles, (long long)d.cus * 16);
+            int* other = nullptr;
+            if (r.sync) {
+                rc = workspace_scratch(ws, stream, n);
+                if (rc) return rc;
+                other = ws->scratch;
+            }
+            int copy_blocks = (int)std::min<long long>(((long long)n + 255) / 256, (long long)d.cus * 8);
+            int sweep = 0, ahead = 4;
+            for (;;) {
+                for (int i = 0; i < ahead; ++i, ++sweep) {
+                    const int* R = L;
+                    int* W = L;
+                    if (r.sync) {
+                        R = (sweep & 1) ? other : L;
+                        W = (sweep & 1) ? L : other;
+                        hipLaunchKernelGGL(k_copy_labels, dim3(std::max(copy_blocks, 1)), dim3(256), 0,
+                                           stream, R, W, (unsigned)n, (const Ctl*)ws->ctl);
+                    }
+                    hipLaunchKernelGGL(ks, dim3((unsigned)grid), dim3(r.block), 0, stream, a, R, W, sweep);
+                }
+                CONTOUR_HIP(hipGetLastError());
+                CONTOUR_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+                CONTOUR_HIP(hipStreamSynchronize(stream));
+                if (ws->host_ctl->state != ST_RUNNING) break;
+                ahead = std::min(ahead * 2, 64);
+            }
+            // The final sweep of a converged synchronous solve changed nothing,
+            // so L and L_u are equal and L already holds the result.  A solve
+            // stopped by the sweep limit may end with the newer state in L_u.
+            if (r.sync && ws->host_ctl->state == ST_LIMIT && (ws->host_ctl->sweeps & 1))
+                CONTOUR_HIP(hipMemcpyAsync(L, other, sizeof(int) * (size_t)n, hipMemcpyDeviceToDevice, stream));
+        }
+    }
+    if (ev_end) CONTOUR_HIP(hipEventRecord(ev_end, stream));
+    if (stats) {
+        hipLaunchKernelGGL(k_write_stats, dim3(1), dim3(64), 0, stream, (const Ctl*)ws->ctl, stats, 0);
+        CONTOUR_HIP(hipGetLastError());
+    }
+    return CONTOUR_OK;
+}
+
+}  // namespace contour
+
+extern "C" {
+
+int contour_cc_ex(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int32_t* labels_inout,
+                  const contour_opts_t* opts, contour_stats_t* stats, contour_stream_t stream)
+{
+    if (m < 0 || n < 0) return CONTOUR_EINVAL;
+    if (n > 0 && !labels_inout) return CONTOUR_EINVAL;
+    if (m > 0 && (!src || !dst)) return CONTOUR_EINVAL;
+    contour::Resolved r;
+    int rc = contour::resolve_opts(opts, &r);
+    if (rc) return rc;
+    if (n == 0) {
+        // No vertices: nothing to label.  Any edge would have an id outside
+        // [0, 0), which the stats report without the edges being read.
+        if (!stats) return CONTOUR_OK;
+        contour::Workspace* ws = nullptr;
+        rc = contour::workspace_for((hipStream_t)stream, &ws);
+        if (rc) return rc;
+        hipLaunchKernelGGL(contour::k_reset_ctl, dim3(1), dim3(64), 0, (hipStream_t)stream, ws->ctl);
+        hipLaunchKernelGGL(contour::k_write_stats, dim3(1), dim3(64), 0, (hipStream_t)stream,
+                           (const contour::Ctl*)ws->ctl, stats, m > 0 ? 1 : 0);
+        CONTOUR_HIP(hipGetLastError());
+        return CONTOUR_OK;
+    }
+    return contour::run_solve(src, dst, m, n, labels_inout, r, stats, (hipStream_t)stream);
+}
+
+int contour_cc(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int32_t* labels_out,
+               contour_stream_t stream)
+{
+    return contour_cc_ex(src, dst, m, n, labels_out, nullptr, nullptr, stream);
+}
+
+}  // extern "C"

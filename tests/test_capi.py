@@ -1,0 +1,68 @@
+"""The C ABI library loads without a GPU and exports every declared symbol."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(contour_[A-Za-z0-9_]+)\s*\(",
+                            text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for need in ("contour_cc", "contour_cc_ex", "contour_batch_plan_create",
+                 "contour_batch_plan_launch", "contour_batch_plan_destroy", "contour_cc_batched",
+                 "contour_status_string", "contour_last_hip_error", "contour_default_opts"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2311_02811_amd as contour
+    lib = ctypes.CDLL(contour.lib_path())
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_host_only_calls_work_without_gpu():
+    import paper_2311_02811_amd as contour
+    lib = contour.load()
+    assert lib.contour_status_string(0) == b"ok"
+    assert lib.contour_status_string(2).startswith(b"edge id")
+    o = contour.make_opts()
+    assert o.order == 2 and o.write_mode == 0 and o.driver == 0
+    assert contour.make_opts(order="full").order == -1
+    assert b"gfx950" in lib.contour_version()
+
+
+def test_argument_errors_are_synchronous_without_touching_the_device():
+    import paper_2311_02811_amd as contour
+    lib = contour.load()
+    # negative sizes and NULL arrays are rejected before any HIP call
+    assert lib.contour_cc(None, None, -1, 4, None, None) == contour.EINVAL
+    assert lib.contour_cc(None, None, 5, 4, None, None) == contour.EINVAL
+    assert lib.contour_cc(None, None, 0, -3, None, None) == contour.EINVAL
+    o = contour.make_opts()
+    o.order = 5000
+    assert lib.contour_cc_ex(None, None, 0, 0, None, ctypes.byref(o), None, None) == contour.EINVAL
+    o = contour.make_opts(update="sync")
+    assert lib.contour_cc_ex(None, None, 0, 0, None, ctypes.byref(o), None, None) == contour.ENOTSUP
+
+
+def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
+    import paper_2311_02811_amd._lib as L
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError):
+        L.load()
