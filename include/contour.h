@@ -156,6 +156,28 @@ typedef struct {
 
 typedef struct contour_plan* contour_plan_t;
 
+/* Per-class choices of a batched plan.  Graphs fall into three classes:
+ *   class 0  n <= lds_max_vertices: one workgroup solves the graph with its
+ *            label array in LDS
+ *   class 1  otherwise, m <= wg_max_edges: one workgroup solves the graph with
+ *            its labels in global memory
+ *   class 2  the rest: several workgroups per graph, sequenced on device by
+ *            per-graph task counters (as the persistent driver)
+ * Zero fields mean "automatic".  The autotuner in the Python package measures
+ * candidates per class and produces this structure. */
+typedef struct {
+    int32_t order;            /* 0: from opts (default 2); 1..CONTOUR_ORDER_MAX or CONTOUR_ORDER_FULL */
+    int32_t block;            /* 0: auto; 256, 512 (and 1024 for classes 0 and 1) */
+    int32_t edges_per_thread; /* 0: auto; 1, 2, 4 or 8 */
+    int32_t reserved;         /* must be 0 */
+} contour_class_tuning_t;
+
+typedef struct {
+    contour_class_tuning_t cls[3];
+    int32_t lds_max_vertices; /* class 0 bound, 0: auto (at most 16384, within LDS per workgroup) */
+    int32_t wg_max_edges;     /* class 1 bound, 0: auto (2^19) */
+} contour_batch_tuning_t;
+
 /* Build a reusable plan: sorts the graphs into size classes (labels in LDS,
  * one workgroup per graph with labels in global memory, several workgroups
  * per graph), picks the per-class order and geometry (opts fields that are
@@ -165,6 +187,13 @@ typedef struct contour_plan* contour_plan_t;
  * CONTOUR_ENOMEM or CONTOUR_EHIP. */
 int contour_batch_plan_create(const contour_batch_t* batch, const contour_opts_t* opts,
                               contour_plan_t* plan_out);
+
+/* As contour_batch_plan_create with explicit per-class choices (NULL: automatic). */
+int contour_batch_plan_create_tuned(const contour_batch_t* batch, const contour_opts_t* opts,
+                                    const contour_batch_tuning_t* tuning, contour_plan_t* plan_out);
+
+/* Number of graphs of the plan in each class (counts[3]); CONTOUR_OK or EINVAL. */
+int contour_batch_plan_classes(contour_plan_t plan, int32_t* counts);
 
 /* Enqueue one solve of every graph of the plan on `stream`.  Enqueues only
  * kernels (no allocation, no host synchronisation, no memset), so it can be

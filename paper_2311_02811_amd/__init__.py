@@ -15,7 +15,7 @@ from __future__ import annotations
 import ctypes
 from dataclasses import dataclass
 
-from ._lib import ContourOpts, load, lib_path  # noqa: F401
+from ._lib import BatchTuning, ContourBatch, ContourOpts, load, lib_path  # noqa: F401
 
 ORDER_FULL = -1
 _SCHED = {"fixed": 0, "11mm": 1, "1m1m": 2}
@@ -131,3 +131,101 @@ def read_stats(st) -> Stats:
 
 def version() -> str:
     return load().contour_version().decode()
+
+
+def make_tuning(classes=None, lds_max_vertices=0, wg_max_edges=0) -> BatchTuning:
+    """Per-class choices for a batched plan: classes is a list of up to three
+    dicts with keys order / block / edges_per_thread (0 or missing = auto)."""
+    t = BatchTuning()
+    for c, spec in enumerate(classes or []):
+        if spec is None:
+            continue
+        o = spec.get("order", 0)
+        t.cls[c].order = ORDER_FULL if o in ("full", ORDER_FULL) else int(o)
+        t.cls[c].block = int(spec.get("block", 0))
+        t.cls[c].edges_per_thread = int(spec.get("edges_per_thread", 0))
+    t.lds_max_vertices = int(lds_max_vertices)
+    t.wg_max_edges = int(wg_max_edges)
+    return t
+
+
+class BatchPlan:
+    """A reusable plan that solves every graph of a CSR-of-graphs batch.
+
+    edge_off, vertex_off: host int64 sequences of length G+1; src, dst: int32
+    CUDA tensors of local ids; labels: int32 CUDA tensor of vertex_off[G]
+    elements (allocated when None).  launch() enqueues one solve on a stream;
+    the plan keeps references to the tensors it was built on.
+    """
+
+    def __init__(self, edge_off, vertex_off, src, dst, labels=None, stats=True, tuning=None,
+                 **opts):
+        import numpy as np
+        torch = _torch()
+        _check_edges(src, dst)
+        self.edge_off = np.ascontiguousarray(edge_off, dtype=np.int64)
+        self.vertex_off = np.ascontiguousarray(vertex_off, dtype=np.int64)
+        self.num_graphs = self.edge_off.size - 1
+        total_n = int(self.vertex_off[-1]) if self.num_graphs > 0 else 0
+        if int(self.edge_off[-1] if self.num_graphs > 0 else 0) != src.numel():
+            raise ValueError("edge_off[-1] must equal the number of edges")
+        self.src, self.dst = src, dst
+        self.labels = labels if labels is not None else torch.empty(
+            max(total_n, 0), dtype=torch.int32, device=src.device)
+        self.stats = torch.zeros((max(self.num_graphs, 1), 4), dtype=torch.int32,
+                                 device=src.device) if stats else None
+        b = ContourBatch()
+        b.num_graphs = self.num_graphs
+        b.h_edge_offsets = self.edge_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        b.h_vertex_offsets = self.vertex_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        b.src = src.data_ptr()
+        b.dst = dst.data_ptr()
+        b.labels_out = self.labels.data_ptr()
+        b.stats_out = self.stats.data_ptr() if stats else None
+        self._batch = b
+        self._opts = make_opts(**opts)
+        self._tuning = tuning
+        h = ctypes.c_void_p()
+        lib = load()
+        if tuning is not None:
+            rc = lib.contour_batch_plan_create_tuned(ctypes.byref(b), ctypes.byref(self._opts),
+                                                     ctypes.byref(tuning), ctypes.byref(h))
+        else:
+            rc = lib.contour_batch_plan_create(ctypes.byref(b), ctypes.byref(self._opts),
+                                               ctypes.byref(h))
+        if rc != OK:
+            raise ContourError(rc, "contour_batch_plan_create")
+        self._h = h
+
+    def classes(self):
+        counts = (ctypes.c_int32 * 3)()
+        load().contour_batch_plan_classes(self._h, counts)
+        return list(counts)
+
+    def launch(self, stream=None):
+        rc = load().contour_batch_plan_launch(self._h, _stream_ptr(stream))
+        if rc != OK:
+            raise ContourError(rc, "contour_batch_plan_launch")
+        return self.labels
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().contour_batch_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cc_batched(edge_off, vertex_off, src, dst, labels=None, stream=None, **opts):
+    """Solve every graph of a batch once (create, launch and destroy a plan)."""
+    plan = BatchPlan(edge_off, vertex_off, src, dst, labels=labels, **opts)
+    try:
+        plan.launch(stream)
+        _torch().cuda.synchronize()
+        return plan.labels, plan.stats
+    finally:
+        plan.close()

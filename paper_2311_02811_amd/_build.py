@@ -1,9 +1,15 @@
-"""Build libcontour.so (HIP for gfx950) in-tree with hipcc."""
+"""Build libcontour.so (HIP for gfx950) in-tree with hipcc.
+
+Each source compiles to an object in parallel, then one link makes the
+shared library next to this file.
+"""
 from __future__ import annotations
 
 import os
 import shutil
 import subprocess
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -22,7 +28,6 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-Wall",
     # keep the compiler from forming packed fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -36,15 +41,29 @@ def hipcc() -> str:
     return path
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source into paper_2311_02811_amd/libcontour.so (always rebuilds)."""
-    tmp = LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-o", tmp]
-    cmd += [os.path.join(CSRC, s) for s in SOURCES]
+def _run(cmd):
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed: %s\n%s%s" % (" ".join(cmd), res.stdout, res.stderr))
+    return res.stdout + res.stderr
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source into paper_2311_02811_amd/libcontour.so (always rebuilds)."""
+    cc = hipcc()
+    with tempfile.TemporaryDirectory(prefix="contour_build_") as tmp:
+        objs, cmds = [], []
+        for src in SOURCES:
+            obj = os.path.join(tmp, os.path.splitext(src)[0] + ".o")
+            objs.append(obj)
+            cmds.append([cc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", "-o", obj,
+                         os.path.join(CSRC, src)])
+        workers = min(len(cmds), max(1, os.cpu_count() or 1))
+        with ThreadPoolExecutor(workers) as ex:
+            logs = list(ex.map(_run, cmds))
+        out = LIB_PATH + ".tmp%d" % os.getpid()
+        logs.append(_run([cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out, *objs]))
     if verbose:
-        print(res.stdout + res.stderr)
-    os.replace(tmp, LIB_PATH)
+        print("".join(logs))
+    os.replace(out, LIB_PATH)
     return LIB_PATH

@@ -38,6 +38,16 @@ class ContourBatch(ctypes.Structure):
                 ("stats_out", ctypes.c_void_p)]
 
 
+class ClassTuning(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("edges_per_thread", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("cls", ClassTuning * 3), ("lds_max_vertices", ctypes.c_int32),
+                ("wg_max_edges", ctypes.c_int32)]
+
+
 # Exported symbols and their C signatures (restype, argtypes).
 SIGNATURES = {
     "contour_default_opts": (None, [ctypes.POINTER(ContourOpts)]),
@@ -50,17 +60,22 @@ SIGNATURES = {
     "contour_last_hip_error": (ctypes.c_int, []),
     "contour_version": (ctypes.c_char_p, []),
     "contour_set_timing_events": (None, [ctypes.c_void_p, ctypes.c_void_p]),
-}
 
-OPTIONAL_SIGNATURES = {
     "contour_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(ContourBatch),
                                                  ctypes.POINTER(ContourOpts),
                                                  ctypes.POINTER(ctypes.c_void_p)]),
+    "contour_batch_plan_create_tuned": (ctypes.c_int, [ctypes.POINTER(ContourBatch),
+                                                       ctypes.POINTER(ContourOpts),
+                                                       ctypes.POINTER(BatchTuning),
+                                                       ctypes.POINTER(ctypes.c_void_p)]),
+    "contour_batch_plan_classes": (ctypes.c_int, [ctypes.c_void_p, c_i32p]),
     "contour_batch_plan_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "contour_batch_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "contour_cc_batched": (ctypes.c_int, [ctypes.POINTER(ContourBatch), ctypes.POINTER(ContourOpts),
                                           ctypes.c_void_p]),
 }
+
+OPTIONAL_SIGNATURES = {}
 
 
 def lib_path() -> str:

@@ -1,39 +1,583 @@
-// contour_batch.hip -- batched solve of many independent graphs.
+// contour_batch.hip -- batched solve of many independent graphs in one plan.
+//
+// A batch is a CSR-of-graphs: graph g has local vertex ids 0..n_g-1 and its
+// own edge range.  Each graph is solved exactly as a single graph would be
+// (same operator, same convergence test); only the placement differs:
+//   class 0  small graphs: one workgroup per graph, label array in LDS, the
+//            whole solve inside the workgroup (barriers separate sweeps)
+//   class 1  medium graphs: one workgroup per graph, labels in global memory
+//   class 2  large graphs: many workgroups per graph; one persistent kernel
+//            spreads the workgroups over the graphs, each graph sequenced by
+//            its own task counters (the single-graph persistent loop)
+// Classes 0 and 1 take graphs from a queue ordered by decreasing edge count
+// (longest first); class 2 runs on a second stream concurrently with them.
+// A launch enqueues kernels and event waits only, so it can be captured into
+// a hipGraph and replayed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
 #include "contour.h"
+#include "contour_device.hpp"
+#include "contour_persistent.hpp"
 #include "contour_runtime.hpp"
+
+namespace contour {
+
+struct BatchJob {
+    long long e0;  // first edge of the graph
+    long long m;   // edge count
+    long long v0;  // first label of the graph
+    int n;         // vertex count
+    int g;         // graph index in the batch (for stats)
+};
+
+struct WgArgs {
+    const int* src;
+    const int* dst;
+    int* labels;
+    contour_stats_t* stats;  // [G] or null
+    const BatchJob* jobs;
+    int njobs;
+    int* counter;  // queue position
+    Sched sched;
+    int max_sweeps;
+    const Ctl* clock;  // t0 for the watchdog
+    unsigned long long watchdog;
+};
+
+// ------------------------------------------------- one graph per workgroup --
+
+template <int EPT, int BLOCK, bool ATOMIC>
+__device__ __forceinline__ void wg_solve(const WgArgs& a, const BatchJob& job, int* L, bool lds)
+{
+    for (int i = threadIdx.x; i < job.n; i += BLOCK) L[i] = i;
+    if (!lds) drain_stores();
+    __syncthreads();
+    const long long tile_edges = (long long)BLOCK * EPT;
+    const long long ntiles = (job.m + tile_edges - 1) / tile_edges;
+    const int* src = a.src + job.e0;
+    const int* dst = a.dst + job.e0;
+    int sweep = 0, last_change = 0, rerr = 0, state = ST_CONVERGED;
+    if (job.m > 0) {
+        for (;;) {
+            const int order = order_of_sweep(a.sched, sweep);
+            const bool pred = run_tiles_order<EPT, BLOCK, ATOMIC>(src, dst, L, L, 0, ntiles, 1, job.m,
+                                                                  (unsigned)job.n, order, rerr);
+            if (!lds) drain_stores();
+            const int any = uniform(__syncthreads_or(pred ? 1 : 0));
+            ++sweep;
+            if (!any) break;
+            last_change = sweep;
+            if (a.max_sweeps > 0 && sweep >= a.max_sweeps) {
+                state = ST_LIMIT;
+                break;
+            }
+            if ((sweep & 15) == 0) {
+                const bool expired = watchdog_expired(a.clock, a.watchdog);
+                if (uniform(__syncthreads_or(expired ? 1 : 0))) {
+                    state = ST_TIMEOUT;
+                    break;
+                }
+            }
+        }
+    }
+    const int anyerr = uniform(__syncthreads_or(rerr));
+    if (lds)
+        for (int i = threadIdx.x; i < job.n; i += BLOCK) a.labels[job.v0 + i] = L[i];
+    if (a.stats && threadIdx.x == 0) {
+        contour_stats_t st;
+        st.status = anyerr ? CONTOUR_ERANGE : (state == ST_CONVERGED ? CONTOUR_OK : CONTOUR_ENOCONV);
+        st.sweeps_executed = sweep;
+        st.sweeps_with_writes = last_change;
+        st.reserved = 0;
+        a.stats[job.g] = st;
+    }
+}
+
+template <int EPT, int BLOCK, bool ATOMIC, bool LDS>
+__global__ __launch_bounds__(BLOCK) void k_batch_wg(WgArgs a)
+{
+    extern __shared__ int lds_labels[];
+    __shared__ int s_job;
+    if (threadIdx.x == 0) s_job = atomicAdd(a.counter, 1);
+    __syncthreads();
+    for (;;) {
+        const int j = uniform(s_job);
+        if (j >= a.njobs) break;
+        const BatchJob job = a.jobs[j];
+        if (LDS)
+            wg_solve<EPT, BLOCK, ATOMIC>(a, job, lds_labels, true);
+        else
+            wg_solve<EPT, BLOCK, ATOMIC>(a, job, a.labels + job.v0, false);
+        __syncthreads();  // every lane has read s_job and finished with LDS
+        if (threadIdx.x == 0) s_job = atomicAdd(a.counter, 1);
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------- many workgroups per graph --
+
+// Workgroups pick a graph: the first graph from the cursor on that is still
+// running and has fewer than want[g] workgroups; when every graph has its
+// share, a workgroup helps the first graph still running.  Inside a graph
+// the persistent loop sequences the sweeps.  A workgroup exits when no
+// graph is running.
+__device__ __forceinline__ int multi_pick(const SolveArgs* graphs, int ngraphs, int* cursor, const int* want)
+{
+    int pick = -1;
+    for (int g = __hip_atomic_load(cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); g < ngraphs; ++g) {
+        Ctl* c = graphs[g].ctl;
+        if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ST_RUNNING) {
+            int e = g;
+            __hip_atomic_compare_exchange_strong(cursor, &e, g + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            continue;
+        }
+        const int j = __hip_atomic_fetch_add(&c->joined, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (j < want[g]) {
+            pick = g;
+            break;
+        }
+    }
+    if (pick < 0) {
+        for (int g = __hip_atomic_load(cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); g < ngraphs; ++g) {
+            if (__hip_atomic_load(&graphs[g].ctl->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ST_RUNNING) {
+                pick = g;
+                break;
+            }
+        }
+    }
+    return pick;
+}
+
+template <int EPT, int BLOCK, bool ATOMIC>
+__global__ __launch_bounds__(BLOCK) void k_batch_multi(const SolveArgs* graphs, int ngraphs, int* cursor,
+                                                       const int* want)
+{
+    __shared__ int s_g;
+    if (threadIdx.x == 0) s_g = multi_pick(graphs, ngraphs, cursor, want);
+    __syncthreads();
+    for (;;) {
+        const int g = uniform(s_g);
+        if (g < 0) break;
+        const SolveArgs a = graphs[g];
+        persistent_solve<EPT, BLOCK, ATOMIC>(a);
+        __syncthreads();  // every lane has read s_g
+        if (threadIdx.x == 0) s_g = multi_pick(graphs, ngraphs, cursor, want);
+        __syncthreads();
+    }
+}
+
+// Reset the queue counters and the watchdog clock of a launch.
+__global__ void k_batch_begin(int* counters, Ctl* clock)
+{
+    if (threadIdx.x < 4) counters[threadIdx.x] = 0;
+    int* p = reinterpret_cast<int*>(clock);
+    if (threadIdx.x < sizeof(Ctl) / sizeof(int)) p[threadIdx.x] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) clock->t0 = wall_clock64();
+}
+
+// Class-2 set-up: block (x, j) initialises part of graph j's labels; block
+// (0, j) also resets graph j's control block.
+__global__ void k_batch_multi_prepare(const SolveArgs* graphs)
+{
+    const SolveArgs& a = graphs[blockIdx.y];
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += gridDim.x * blockDim.x)
+        a.L[i] = (int)i;
+    if (blockIdx.x == 0) {
+        int* p = reinterpret_cast<int*>(a.ctl);
+        if (threadIdx.x < sizeof(Ctl) / sizeof(int)) p[threadIdx.x] = 0;
+        __syncthreads();
+        if (threadIdx.x == 0) a.ctl->t0 = wall_clock64();
+    }
+}
+
+__global__ void k_batch_multi_stats(const SolveArgs* graphs, const int* gidx, int ngraphs,
+                                    contour_stats_t* stats)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ngraphs) return;
+    const Ctl* c = graphs[j].ctl;
+    contour_stats_t st;
+    st.status = c->range_err ? CONTOUR_ERANGE
+                             : ((c->state == ST_LIMIT || c->state == ST_TIMEOUT) ? CONTOUR_ENOCONV : CONTOUR_OK);
+    st.sweeps_executed = c->sweeps;
+    st.sweeps_with_writes = c->last_change;
+    st.reserved = 0;
+    stats[gidx[j]] = st;
+}
+
+// ------------------------------------------------------------- dispatch --
+
+typedef void (*wg_fn)(WgArgs);
+typedef void (*multi_fn)(const SolveArgs*, int, int*, const int*);
+
+template <int BLOCK, bool ATOMIC, bool LDS>
+static wg_fn pick_wg_e(int ept)
+{
+    switch (ept) {
+    case 1: return k_batch_wg<1, BLOCK, ATOMIC, LDS>;
+    case 2: return k_batch_wg<2, BLOCK, ATOMIC, LDS>;
+    default: return k_batch_wg<4, BLOCK, ATOMIC, LDS>;
+    }
+}
+
+template <bool ATOMIC, bool LDS>
+static wg_fn pick_wg_b(int block, int ept)
+{
+    if (block == 1024) return pick_wg_e<1024, ATOMIC, LDS>(ept);
+    if (block == 512) return pick_wg_e<512, ATOMIC, LDS>(ept);
+    return pick_wg_e<256, ATOMIC, LDS>(ept);
+}
+
+static wg_fn pick_wg(int block, int ept, bool atomic, bool lds)
+{
+    if (atomic) return lds ? pick_wg_b<true, true>(block, ept) : pick_wg_b<true, false>(block, ept);
+    return lds ? pick_wg_b<false, true>(block, ept) : pick_wg_b<false, false>(block, ept);
+}
+
+template <int BLOCK, bool ATOMIC>
+static multi_fn pick_multi_e(int ept)
+{
+    switch (ept) {
+    case 1: return k_batch_multi<1, BLOCK, ATOMIC>;
+    case 2: return k_batch_multi<2, BLOCK, ATOMIC>;
+    case 8: return k_batch_multi<8, BLOCK, ATOMIC>;
+    default: return k_batch_multi<4, BLOCK, ATOMIC>;
+    }
+}
+
+static multi_fn pick_multi(int block, int ept, bool atomic)
+{
+    if (block == 512) return atomic ? pick_multi_e<512, true>(ept) : pick_multi_e<512, false>(ept);
+    return atomic ? pick_multi_e<256, true>(ept) : pick_multi_e<256, false>(ept);
+}
+
+}  // namespace contour
+
+// ----------------------------------------------------------------- plan --
+
+struct contour_plan {
+    int device = -1;
+    int G = 0;
+    int counts[3] = {0, 0, 0};
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int* d_counters = nullptr;         // [0] class-0 queue, [1] class-1 queue, [2] class-2 cursor
+    contour::Ctl* d_clock = nullptr;   // class 0/1 watchdog clock
+    contour::BatchJob* d_jobs = nullptr;  // class 0 jobs then class 1 jobs
+    contour::SolveArgs* d_graphs = nullptr;  // class 2
+    contour::Ctl* d_ctl = nullptr;     // class 2 control blocks
+    int* d_want = nullptr;
+    int* d_gidx = nullptr;
+    contour::WgArgs wg[2];
+    contour::wg_fn wg_kernel[2] = {nullptr, nullptr};
+    unsigned wg_grid[2] = {0, 0};
+    int wg_block[2] = {256, 256};
+    size_t wg_lds[2] = {0, 0};
+    contour::multi_fn multi_kernel = nullptr;
+    unsigned multi_grid = 0;
+    int multi_block = 256;
+    unsigned prep_x = 1;
+    contour_stats_t* stats = nullptr;
+};
+
+namespace contour {
+
+static void free_plan(contour_plan* p)
+{
+    if (!p) return;
+    if (p->d_counters) (void)hipFree(p->d_counters);
+    if (p->d_clock) (void)hipFree(p->d_clock);
+    if (p->d_jobs) (void)hipFree(p->d_jobs);
+    if (p->d_graphs) (void)hipFree(p->d_graphs);
+    if (p->d_ctl) (void)hipFree(p->d_ctl);
+    if (p->d_want) (void)hipFree(p->d_want);
+    if (p->d_gidx) (void)hipFree(p->d_gidx);
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+    if (p->side) (void)hipStreamDestroy(p->side);
+    delete p;
+}
+
+static int class_geometry(const contour_batch_tuning_t* t, int cls, int* block, int* ept, int* order,
+                          int default_order)
+{
+    int b = t ? t->cls[cls].block : 0;
+    int e = t ? t->cls[cls].edges_per_thread : 0;
+    int o = t ? t->cls[cls].order : 0;
+    if (t && t->cls[cls].reserved != 0) return CONTOUR_EINVAL;
+    if (b == 0) b = cls == 2 ? 256 : 512;
+    if (e == 0) e = cls == 0 ? 1 : (cls == 1 ? 2 : 4);
+    if (o == 0) o = default_order;
+    if (b != 256 && b != 512 && !(b == 1024 && cls < 2)) return CONTOUR_EINVAL;
+    if (e != 1 && e != 2 && e != 4 && !(e == 8 && cls == 2)) return CONTOUR_EINVAL;
+    if (!(o == CONTOUR_ORDER_FULL || (o >= 1 && o <= CONTOUR_ORDER_MAX))) return CONTOUR_EINVAL;
+    *block = b;
+    *ept = e;
+    *order = o;
+    return CONTOUR_OK;
+}
+
+template <typename T>
+static hipError_t upload(T** dst, const std::vector<T>& v)
+{
+    *dst = nullptr;
+    if (v.empty()) return hipSuccess;
+    hipError_t e = hipMalloc((void**)dst, sizeof(T) * v.size());
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
+}
+
+static int create_plan(const contour_batch_t* b, const contour_opts_t* opts, const contour_batch_tuning_t* t,
+                       contour_plan_t* out)
+{
+    if (!b || !out) return CONTOUR_EINVAL;
+    *out = nullptr;
+    const int G = b->num_graphs;
+    if (G < 0 || (G > 0 && (!b->h_edge_offsets || !b->h_vertex_offsets))) return CONTOUR_EINVAL;
+    Resolved r;
+    int rc = resolve_opts(opts, &r);
+    if (rc) return rc;
+    if (r.sync || r.driver != CONTOUR_DRIVER_PERSISTENT || r.warm) return CONTOUR_ENOTSUP;
+    const int64_t* eo = b->h_edge_offsets;
+    const int64_t* vo = b->h_vertex_offsets;
+    if (G > 0 && (eo[0] != 0 || vo[0] != 0)) return CONTOUR_EINVAL;
+    for (int g = 0; g < G; ++g) {
+        if (eo[g + 1] < eo[g] || vo[g + 1] < vo[g] || vo[g + 1] - vo[g] > 0x7fffffffLL) return CONTOUR_EINVAL;
+    }
+    const int64_t total_m = G ? eo[G] : 0, total_n = G ? vo[G] : 0;
+    if (total_m > 0 && (!b->src || !b->dst)) return CONTOUR_EINVAL;
+    if (total_n > 0 && !b->labels_out) return CONTOUR_EINVAL;
+
+    DeviceInfo d;
+    rc = device_info(&d);
+    if (rc) return rc;
+    int lds_max = t ? t->lds_max_vertices : 0;
+    if (lds_max < 0) return CONTOUR_EINVAL;
+    const int lds_cap = std::min(16384, (d.max_lds_per_block - 1024) / 4);
+    if (lds_max == 0 || lds_max > (d.max_lds_per_block - 1024) / 4) lds_max = lds_cap;
+    long long wg_max = t ? t->wg_max_edges : 0;
+    if (wg_max < 0) return CONTOUR_EINVAL;
+    if (wg_max == 0) wg_max = 1 << 19;
+
+    int block[3], ept[3], order[3];
+    for (int c = 0; c < 3; ++c) {
+        rc = class_geometry(t, c, &block[c], &ept[c], &order[c], r.sched.order);
+        if (rc) return rc;
+    }
+
+    contour_plan* p = new (std::nothrow) contour_plan();
+    if (!p) return CONTOUR_ENOMEM;
+    p->G = G;
+    p->stats = b->stats_out;
+    CONTOUR_HIP(hipGetDevice(&p->device));
+
+    // classify; longest graphs first within each class
+    std::vector<int> idx(G);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+        return eo[x + 1] - eo[x] > eo[y + 1] - eo[y];
+    });
+    std::vector<BatchJob> jobs[2];
+    std::vector<int> big;
+    for (int g : idx) {
+        BatchJob j;
+        j.e0 = eo[g];
+        j.m = eo[g + 1] - eo[g];
+        j.v0 = vo[g];
+        j.n = (int)(vo[g + 1] - vo[g]);
+        j.g = g;
+        if (j.n <= lds_max)
+            jobs[0].push_back(j);
+        else if (j.m <= wg_max)
+            jobs[1].push_back(j);
+        else
+            big.push_back(g);
+    }
+    p->counts[0] = (int)jobs[0].size();
+    p->counts[1] = (int)jobs[1].size();
+    p->counts[2] = (int)big.size();
+
+    hipError_t e = hipMalloc((void**)&p->d_counters, 4 * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_clock, sizeof(Ctl));
+    std::vector<BatchJob> all = jobs[0];
+    all.insert(all.end(), jobs[1].begin(), jobs[1].end());
+    if (e == hipSuccess) e = upload(&p->d_jobs, all);
+    if (e != hipSuccess) {
+        free_plan(p);
+        return hip_fail(e);
+    }
+    const unsigned long long wd = watchdog_ticks(d);
+    for (int c = 0; c < 2; ++c) {
+        WgArgs& a = p->wg[c];
+        a.src = b->src;
+        a.dst = b->dst;
+        a.labels = b->labels_out;
+        a.stats = b->stats_out;
+        a.jobs = p->d_jobs + (c == 0 ? 0 : jobs[0].size());
+        a.njobs = (int)jobs[c].size();
+        a.counter = p->d_counters + c;
+        a.sched = r.sched;
+        a.sched.order = order[c];
+        a.max_sweeps = r.max_sweeps;
+        a.clock = p->d_clock;
+        a.watchdog = wd;
+        p->wg_block[c] = block[c];
+        p->wg_kernel[c] = pick_wg(block[c], ept[c], r.atomic, c == 0);
+        int max_n = 0;
+        for (const BatchJob& j : jobs[c]) max_n = std::max(max_n, j.n);
+        p->wg_lds[c] = c == 0 ? sizeof(int) * (size_t)std::max(max_n, 1) : 0;
+        if (c == 0)
+            (void)hipFuncSetAttribute((const void*)p->wg_kernel[c], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)p->wg_lds[c]);
+        int occ = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)p->wg_kernel[c], block[c],
+                                                         p->wg_lds[c]);
+        if (e != hipSuccess) {
+            free_plan(p);
+            return hip_fail(e);
+        }
+        p->wg_grid[c] = (unsigned)std::max<long long>(
+            0, std::min<long long>((long long)std::max(occ, 1) * d.cus, (long long)jobs[c].size()));
+    }
+
+    if (!big.empty()) {
+        std::vector<Ctl> zero(big.size());
+        std::memset(zero.data(), 0, sizeof(Ctl) * zero.size());
+        e = upload(&p->d_ctl, zero);
+        std::vector<SolveArgs> graphs;
+        std::vector<int> want;
+        Resolved rc2 = r;
+        rc2.sched.order = order[2];
+        rc2.block = block[2];
+        rc2.ept = ept[2];
+        rc2.grid = 0;
+        p->multi_kernel = pick_multi(block[2], ept[2], r.atomic);
+        int occ = 0;
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)p->multi_kernel, block[2], 0);
+        const long long resident = (long long)std::max(occ, 1) * d.cus;
+        long long sum_want = 0;
+        unsigned max_n = 1;
+        for (size_t k = 0; e == hipSuccess && k < big.size(); ++k) {
+            const int g = big[k];
+            PersistentLaunch pl;
+            int rr = prepare_persistent(d, rc2, b->src + eo[g], b->dst + eo[g], eo[g + 1] - eo[g],
+                                        (int)(vo[g + 1] - vo[g]), b->labels_out + vo[g], p->d_ctl + k, &pl);
+            if (rr) {
+                free_plan(p);
+                return rr;
+            }
+            graphs.push_back(pl.args);
+            long long w = std::max<long long>(1, std::min<long long>(resident, (pl.args.tasks + 3) / 4));
+            want.push_back((int)w);
+            sum_want += w;
+            max_n = std::max(max_n, pl.args.n);
+        }
+        if (e == hipSuccess) e = upload(&p->d_graphs, graphs);
+        if (e == hipSuccess) e = upload(&p->d_want, want);
+        if (e == hipSuccess) e = upload(&p->d_gidx, big);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            free_plan(p);
+            return hip_fail(e);
+        }
+        p->multi_block = block[2];
+        p->multi_grid = (unsigned)std::min<long long>(resident, sum_want);
+        p->prep_x = (unsigned)std::max<long long>(1, std::min<long long>(((long long)max_n + 255) / 256, 1024));
+    }
+    *out = p;
+    return CONTOUR_OK;
+}
+
+static int launch_plan(contour_plan* p, hipStream_t stream)
+{
+    if (!p) return CONTOUR_EINVAL;
+    if (p->G == 0) return CONTOUR_OK;
+    hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, stream, p->d_counters, p->d_clock);
+    CONTOUR_HIP(hipGetLastError());
+    const int nbig = p->counts[2];
+    if (nbig > 0) {
+        CONTOUR_HIP(hipEventRecord(p->ev_fork, stream));
+        CONTOUR_HIP(hipStreamWaitEvent(p->side, p->ev_fork, 0));
+        hipLaunchKernelGGL(k_batch_multi_prepare, dim3(p->prep_x, nbig), dim3(256), 0, p->side,
+                           (const SolveArgs*)p->d_graphs);
+        hipLaunchKernelGGL(p->multi_kernel, dim3(p->multi_grid), dim3(p->multi_block), 0, p->side,
+                           (const SolveArgs*)p->d_graphs, nbig, p->d_counters + 2, (const int*)p->d_want);
+        if (p->stats)
+            hipLaunchKernelGGL(k_batch_multi_stats, dim3((nbig + 63) / 64), dim3(64), 0, p->side,
+                               (const SolveArgs*)p->d_graphs, (const int*)p->d_gidx, nbig, p->stats);
+        CONTOUR_HIP(hipGetLastError());
+        CONTOUR_HIP(hipEventRecord(p->ev_join, p->side));
+    }
+    for (int c = 1; c >= 0; --c) {
+        if (p->wg_grid[c] == 0) continue;
+        hipLaunchKernelGGL(p->wg_kernel[c], dim3(p->wg_grid[c]), dim3(p->wg_block[c]), p->wg_lds[c], stream,
+                           p->wg[c]);
+        CONTOUR_HIP(hipGetLastError());
+    }
+    if (nbig > 0) CONTOUR_HIP(hipStreamWaitEvent(stream, p->ev_join, 0));
+    return CONTOUR_OK;
+}
+
+}  // namespace contour
 
 extern "C" {
 
-int contour_batch_plan_create(const contour_batch_t* batch, const contour_opts_t* opts,
-                              contour_plan_t* plan_out)
+int contour_batch_plan_create_tuned(const contour_batch_t* batch, const contour_opts_t* opts,
+                                    const contour_batch_tuning_t* tuning, contour_plan_t* plan_out)
 {
-    (void)batch;
-    (void)opts;
-    if (plan_out) *plan_out = nullptr;
-    return CONTOUR_ENOTSUP;
+    return contour::create_plan(batch, opts, tuning, plan_out);
+}
+
+int contour_batch_plan_create(const contour_batch_t* batch, const contour_opts_t* opts, contour_plan_t* plan_out)
+{
+    return contour::create_plan(batch, opts, nullptr, plan_out);
+}
+
+int contour_batch_plan_classes(contour_plan_t plan, int32_t* counts)
+{
+    if (!plan || !counts) return CONTOUR_EINVAL;
+    for (int c = 0; c < 3; ++c) counts[c] = plan->counts[c];
+    return CONTOUR_OK;
 }
 
 int contour_batch_plan_launch(contour_plan_t plan, contour_stream_t stream)
 {
-    (void)plan;
-    (void)stream;
-    return CONTOUR_ENOTSUP;
+    return contour::launch_plan(plan, (hipStream_t)stream);
 }
 
 int contour_batch_plan_destroy(contour_plan_t plan)
 {
-    (void)plan;
+    if (!plan) return CONTOUR_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && dev == plan->device) (void)hipDeviceSynchronize();
+    contour::free_plan(plan);
     return CONTOUR_OK;
 }
 
 int contour_cc_batched(const contour_batch_t* batch, const contour_opts_t* opts, contour_stream_t stream)
 {
-    (void)batch;
-    (void)opts;
-    (void)stream;
-    return CONTOUR_ENOTSUP;
+    contour_plan_t p = nullptr;
+    int rc = contour::create_plan(batch, opts, nullptr, &p);
+    if (rc) return rc;
+    rc = contour::launch_plan(p, (hipStream_t)stream);
+    if (rc == CONTOUR_OK) {
+        hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess) rc = contour::hip_fail(e);
+    }
+    contour::free_plan(p);
+    return rc;
 }
 
 }  // extern "C"

@@ -60,6 +60,21 @@ __device__ __forceinline__ int order_of_sweep(const Sched& s, int sweep)
     return s.order;
 }
 
+// Arguments of one single-graph solve.
+struct SolveArgs {
+    const int* src;
+    const int* dst;
+    int* L;
+    long long m;
+    unsigned n;
+    long long tasks;     // persistent driver: tasks per sweep
+    int tiles_per_task;  // persistent driver
+    Sched sched;
+    int max_sweeps;      // 0 = no limit
+    Ctl* ctl;
+    unsigned long long watchdog;  // wall-clock ticks a solve may run, 0 = unbounded
+};
+
 // Edge ids are streamed once per sweep: non-temporal loads keep them from
 // displacing the label array in the caches.
 __device__ __forceinline__ int ld_edge(const int* p) { return __builtin_nontemporal_load(p); }
@@ -309,6 +324,21 @@ __device__ __forceinline__ bool run_tiles_order(const int* __restrict__ src, con
         if (h < 0 || (unsigned)h > n) h = (int)n;
         return run_tiles<0, EPT, BLOCK, ATOMIC>(src, dst, R, W, first, count, stride, m, n, h, rerr);
     }
+}
+
+// Loop control read back from shared memory must be visibly uniform: the
+// compiler cannot tell that every lane read the same word, and a loop whose
+// exit looks divergent may be restructured so that some lanes of a wave go
+// round a barrier again while others wait outside it.  Reading the value
+// through readfirstlane makes it a scalar and the branch uniform.
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ long long uniform(long long x)
+{
+    const unsigned long long u = (unsigned long long)x;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
 }
 
 // Wait until every store this thread issued has completed, so a barrier that

@@ -70,6 +70,27 @@ unsigned long long watchdog_ticks(const DeviceInfo& d);
 // Per-thread timing events set by contour_set_timing_events (may be null).
 void timing_events(hipEvent_t* begin, hipEvent_t* end);
 
+// A prepared single-graph persistent solve: everything needed to enqueue it
+// without allocating (used by contour_cc_ex and by batched plans).
+struct PersistentLaunch {
+    void (*kernel)(SolveArgs);  // null when m == 0
+    SolveArgs args;
+    unsigned grid;
+    int block;
+    unsigned init_blocks;
+    int warm;
+    int n;
+};
+
+// Resolve geometry and fill *out for a solve that uses control block `ctl`.
+int prepare_persistent(const DeviceInfo& d, const Resolved& r, const int* src, const int* dst,
+                       long long m, int n, int* L, Ctl* ctl, PersistentLaunch* out);
+
+// Enqueue: reset the control block, initialise (or check) labels, run the
+// persistent sweep kernel, write stats.  Optional events bracket the sweeps.
+int enqueue_persistent(const PersistentLaunch& p, contour_stats_t* stats, hipStream_t stream,
+                       hipEvent_t ev_begin, hipEvent_t ev_end);
+
 // Validate opts and fill defaults; returns CONTOUR_OK or CONTOUR_EINVAL /
 // CONTOUR_ENOTSUP.
 int resolve_opts(const contour_opts_t* opts, Resolved* r);

@@ -8,23 +8,10 @@
 
 #include "contour.h"
 #include "contour_device.hpp"
+#include "contour_persistent.hpp"
 #include "contour_runtime.hpp"
 
 namespace contour {
-
-struct SolveArgs {
-    const int* src;
-    const int* dst;
-    int* L;
-    long long m;
-    unsigned n;
-    long long tasks;     // persistent driver: tasks per sweep
-    int tiles_per_task;  // persistent driver
-    Sched sched;
-    int max_sweeps;      // 0 = no limit
-    Ctl* ctl;
-    unsigned long long watchdog;  // wall-clock ticks a solve may run, 0 = unbounded
-};
 
 // ------------------------------------------------------------ set-up ----
 
@@ -70,88 +57,12 @@ __global__ void k_write_stats(const Ctl* c, contour_stats_t* out, int range_err)
 }
 
 // ------------------------------------------------- persistent driver ----
-// One launch for the whole solve.  Task t covers edge chunk t % T of sweep
-// t / T (T tasks per sweep).  A workgroup takes the next task from a counter;
-// before working on sweep s it waits until all T tasks of sweep s-1 are done,
-// and if sweep s-1 changed nothing the solve has converged.  A workgroup only
-// ever waits for tasks that running workgroups have already taken, so the
-// scheme needs no co-residency and cannot deadlock.  Task completion is a
-// release (label stores drained, then an agent-scope release add), and the
-// wait is an acquire, so sweep s reads every store of sweeps < s.
+// One launch for the whole solve; the sweep loop is persistent_solve() in
+// contour_persistent.hpp.
 template <int EPT, int BLOCK, bool ATOMIC>
 __global__ __launch_bounds__(BLOCK) void k_persistent(SolveArgs a)
 {
-    __shared__ long long s_task;
-    __shared__ int s_go;
-    Ctl* c = a.ctl;
-    const long long tile_edges = (long long)BLOCK * EPT;
-    for (;;) {
-        if (threadIdx.x == 0) {
-            int go = 0;
-            long long t = 0;
-            if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ST_RUNNING) {
-                t = (long long)__hip_atomic_fetch_add(&c->next_task, 1ULL, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-                long long sweep = t / a.tasks;
-                if (sweep > 0) {
-                    const unsigned long long need = (unsigned long long)(sweep * a.tasks);
-                    while (__hip_atomic_load(&c->done_task, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                        if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ST_RUNNING)
-                            break;
-                        if (watchdog_expired(c, a.watchdog)) {
-                            int expect = ST_RUNNING;
-                            __hip_atomic_compare_exchange_strong(&c->state, &expect, (int)ST_TIMEOUT,
-                                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                                 __HIP_MEMORY_SCOPE_AGENT);
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(2);
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ST_RUNNING) {
-                    int lc = __hip_atomic_load(&c->last_change, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    int st = ST_RUNNING;
-                    if (sweep > 0 && lc <= sweep - 1)
-                        st = ST_CONVERGED;
-                    else if (a.max_sweeps > 0 && sweep >= a.max_sweeps)
-                        st = ST_LIMIT;
-                    else if (watchdog_expired(c, a.watchdog))
-                        st = ST_TIMEOUT;
-                    if (st == ST_RUNNING) {
-                        go = 1;
-                    } else {
-                        int expect = ST_RUNNING;
-                        if (__hip_atomic_compare_exchange_strong(&c->state, &expect, st, __ATOMIC_RELAXED,
-                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                            __hip_atomic_store(&c->sweeps, (int)sweep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                }
-            }
-            s_go = go;
-            s_task = t;
-        }
-        __syncthreads();
-        if (!s_go) break;
-        const long long t = s_task;
-        const long long sweep = t / a.tasks;
-        const long long chunk = t - sweep * a.tasks;
-        const int order = order_of_sweep(a.sched, (int)sweep);
-        bool pred = false;
-        int rerr = 0;
-        pred = run_tiles_order<EPT, BLOCK, ATOMIC>(a.src, a.dst, a.L, a.L, chunk * a.tiles_per_task,
-                                                   a.tiles_per_task, 1, a.m, a.n, order, rerr);
-        drain_stores();
-        const int any = __syncthreads_or(pred ? 1 : 0);
-        const int anyerr = __syncthreads_or(rerr);
-        if (threadIdx.x == 0) {
-            if (any)
-                __hip_atomic_fetch_max(&c->last_change, (int)sweep + 1, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-            if (anyerr) __hip_atomic_store(&c->range_err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&c->done_task, 1ULL, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+    persistent_solve<EPT, BLOCK, ATOMIC>(a);
 }
 
 // ------------------------------------------------- host-loop driver -----
@@ -188,8 +99,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SolveArgs a, const int* R, int*
     const long long mine = blockIdx.x < ntiles ? (ntiles - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
     pred = run_tiles_order<EPT, BLOCK, ATOMIC>(a.src, a.dst, R, W, blockIdx.x, mine, gridDim.x, a.m, a.n,
                                                order, rerr);
-    const int any = __syncthreads_or(pred ? 1 : 0);
-    const int anyerr = __syncthreads_or(rerr);
+    const int any = uniform(__syncthreads_or(pred ? 1 : 0));
+    const int anyerr = uniform(__syncthreads_or(rerr));
     if (threadIdx.x == 0) {
         if (any) c->last_change = sweep + 1;
         if (anyerr) c->range_err = 1;
@@ -242,28 +153,89 @@ static void auto_geometry(const DeviceInfo& d, long long m, Resolved* r)
     }
 }
 
-static int run_solve(const int* src, const int* dst, long long m, int n, int* L, const Resolved& r0,
-                     contour_stats_t* stats, hipStream_t stream)
+int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, const int* dst,
+                       long long m, int n, int* L, Ctl* ctl, PersistentLaunch* out)
 {
-    DeviceInfo d;
-    int rc = device_info(&d);
-    if (rc) return rc;
-    Workspace* ws = nullptr;
-    rc = workspace_for(stream, &ws);
-    if (rc) return rc;
     Resolved r = r0;
     auto_geometry(d, m, &r);
-
-    hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, stream, ws->ctl);
-    {
-        int blocks = (int)std::min<long long>(((long long)n + 255) / 256, (long long)d.cus * 8);
-        hipLaunchKernelGGL(k_init_labels, dim3(std::max(blocks, 1)), dim3(256), 0, stream, L,
-                           (unsigned)n, r.warm ? 1 : 0, ws->ctl);
+    PersistentLaunch p;
+    p.n = n;
+    p.warm = r.warm ? 1 : 0;
+    p.init_blocks = (unsigned)std::max<long long>(
+        1, std::min<long long>(((long long)n + 255) / 256, (long long)d.cus * 8));
+    p.block = r.block;
+    SolveArgs& a = p.args;
+    a.src = src;
+    a.dst = dst;
+    a.L = L;
+    a.m = m;
+    a.n = (unsigned)n;
+    a.sched = r.sched;
+    a.max_sweeps = r.max_sweeps;
+    a.ctl = ctl;
+    a.watchdog = watchdog_ticks(d);
+    a.tiles_per_task = 1;
+    a.tasks = 0;
+    p.kernel = nullptr;
+    p.grid = 0;
+    if (m > 0) {
+        sweep_fn ks;
+        pick_kernels(r.block, r.ept, r.atomic, &p.kernel, &ks);
+        const long long tile_edges = (long long)r.block * r.ept;
+        const long long ntiles = (m + tile_edges - 1) / tile_edges;
+        int occ = 0;
+        CONTOUR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)p.kernel, r.block, 0));
+        const long long resident = (long long)std::max(occ, 1) * d.cus;
+        int tpt = r.chunk_tiles;
+        if (tpt == 0) {
+            // about 4 tasks per resident workgroup and sweep, at most 16 tiles each
+            tpt = (int)std::max<long long>(1, std::min<long long>(16, ntiles / (4 * resident)));
+        }
+        a.tiles_per_task = tpt;
+        a.tasks = (ntiles + tpt - 1) / tpt;
+        p.grid = (unsigned)(r.grid ? r.grid : std::min<long long>(resident, a.tasks));
     }
-    CONTOUR_HIP(hipGetLastError());
+    *out = p;
+    return CONTOUR_OK;
+}
 
+int enqueue_persistent(const PersistentLaunch& p, contour_stats_t* stats, hipStream_t stream,
+                       hipEvent_t ev_begin, hipEvent_t ev_end)
+{
+    Ctl* ctl = p.args.ctl;
+    hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, stream, ctl);
+    hipLaunchKernelGGL(k_init_labels, dim3(p.init_blocks), dim3(256), 0, stream, p.args.L,
+                       (unsigned)p.n, p.warm, ctl);
+    CONTOUR_HIP(hipGetLastError());
+    if (ev_begin) CONTOUR_HIP(hipEventRecord(ev_begin, stream));
+    if (p.kernel) {
+        hipLaunchKernelGGL(p.kernel, dim3(p.grid), dim3(p.block), 0, stream, p.args);
+        CONTOUR_HIP(hipGetLastError());
+    }
+    if (ev_end) CONTOUR_HIP(hipEventRecord(ev_end, stream));
+    if (stats) {
+        hipLaunchKernelGGL(k_write_stats, dim3(1), dim3(64), 0, stream, (const Ctl*)ctl, stats, 0);
+        CONTOUR_HIP(hipGetLastError());
+    }
+    return CONTOUR_OK;
+}
+
+// Host-sequenced sweeps (asynchronous or synchronous update).  Blocks the
+// calling thread: it reads the control block every few sweeps.
+static int run_hostloop(const DeviceInfo& d, const Resolved& r0, const int* src, const int* dst,
+                        long long m, int n, int* L, Workspace* ws, contour_stats_t* stats,
+                        hipStream_t stream)
+{
+    Resolved r = r0;
+    auto_geometry(d, m, &r);
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;
     timing_events(&ev_begin, &ev_end);
+    hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, stream, ws->ctl);
+    const unsigned init_blocks = (unsigned)std::max<long long>(
+        1, std::min<long long>(((long long)n + 255) / 256, (long long)d.cus * 8));
+    hipLaunchKernelGGL(k_init_labels, dim3(init_blocks), dim3(256), 0, stream, L, (unsigned)n,
+                       r.warm ? 1 : 0, ws->ctl);
+    CONTOUR_HIP(hipGetLastError());
     if (ev_begin) CONTOUR_HIP(hipEventRecord(ev_begin, stream));
     if (m > 0) {
         persistent_fn kp;
@@ -281,57 +253,39 @@ static int run_solve(const int* src, const int* dst, long long m, int n, int* L,
         a.watchdog = watchdog_ticks(d);
         const long long tile_edges = (long long)r.block * r.ept;
         const long long ntiles = (m + tile_edges - 1) / tile_edges;
-        if (r.driver == CONTOUR_DRIVER_PERSISTENT) {
-            int occ = 0;
-            CONTOUR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kp, r.block, 0));
-            long long resident = (long long)std::max(occ, 1) * d.cus;
-            int tpt = r.chunk_tiles;
-            if (tpt == 0) {
-                // about 4 tasks per resident workgroup and sweep, at most 16 tiles each
-                tpt = (int)std::max<long long>(1, std::min<long long>(16, ntiles / (4 * resident)));
-            }
-            a.tiles_per_task = tpt;
-            a.tasks = (ntiles + tpt - 1) / tpt;
-            long long grid = r.grid ? r.grid : std::min<long long>(resident, a.tasks);
-            a.L = L;
-            hipLaunchKernelGGL(kp, dim3((unsigned)grid), dim3(r.block), 0, stream, a);
-            CONTOUR_HIP(hipGetLastError());
-        } else {
-            a.tiles_per_task = 1;
-            a.tasks = ntiles;
-            long long grid = r.grid ? r.grid : std::min<long long>(ntiles, (long long)d.cus * 16);
-            int* other = nullptr;
-            if (r.sync) {
-                rc = workspace_scratch(ws, stream, n);
-                if (rc) return rc;
-                other = ws->scratch;
-            }
-            int copy_blocks = (int)std::min<long long>(((long long)n + 255) / 256, (long long)d.cus * 8);
-            int sweep = 0, ahead = 4;
-            for (;;) {
-                for (int i = 0; i < ahead; ++i, ++sweep) {
-                    const int* R = L;
-                    int* W = L;
-                    if (r.sync) {
-                        R = (sweep & 1) ? other : L;
-                        W = (sweep & 1) ? L : other;
-                        hipLaunchKernelGGL(k_copy_labels, dim3(std::max(copy_blocks, 1)), dim3(256), 0,
-                                           stream, R, W, (unsigned)n, (const Ctl*)ws->ctl);
-                    }
-                    hipLaunchKernelGGL(ks, dim3((unsigned)grid), dim3(r.block), 0, stream, a, R, W, sweep);
-                }
-                CONTOUR_HIP(hipGetLastError());
-                CONTOUR_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
-                CONTOUR_HIP(hipStreamSynchronize(stream));
-                if (ws->host_ctl->state != ST_RUNNING) break;
-                ahead = std::min(ahead * 2, 64);
-            }
-            // The final sweep of a converged synchronous solve changed nothing,
-            // so L and L_u are equal and L already holds the result.  A solve
-            // stopped by the sweep limit may end with the newer state in L_u.
-            if (r.sync && ws->host_ctl->state == ST_LIMIT && (ws->host_ctl->sweeps & 1))
-                CONTOUR_HIP(hipMemcpyAsync(L, other, sizeof(int) * (size_t)n, hipMemcpyDeviceToDevice, stream));
+        a.tiles_per_task = 1;
+        a.tasks = ntiles;
+        const long long grid = r.grid ? r.grid : std::min<long long>(ntiles, (long long)d.cus * 16);
+        int* other = nullptr;
+        if (r.sync) {
+            int rc = workspace_scratch(ws, stream, n);
+            if (rc) return rc;
+            other = ws->scratch;
         }
+        int sweep = 0, ahead = 4;
+        for (;;) {
+            for (int i = 0; i < ahead; ++i, ++sweep) {
+                const int* R = L;
+                int* W = L;
+                if (r.sync) {
+                    R = (sweep & 1) ? other : L;
+                    W = (sweep & 1) ? L : other;
+                    hipLaunchKernelGGL(k_copy_labels, dim3(init_blocks), dim3(256), 0, stream, R, W,
+                                       (unsigned)n, (const Ctl*)ws->ctl);
+                }
+                hipLaunchKernelGGL(ks, dim3((unsigned)grid), dim3(r.block), 0, stream, a, R, W, sweep);
+            }
+            CONTOUR_HIP(hipGetLastError());
+            CONTOUR_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+            CONTOUR_HIP(hipStreamSynchronize(stream));
+            if (ws->host_ctl->state != ST_RUNNING) break;
+            ahead = std::min(ahead * 2, 64);
+        }
+        // The final sweep of a converged synchronous solve changed nothing,
+        // so L and L_u are equal and L already holds the result.  A solve
+        // stopped by the sweep limit may end with the newer state in L_u.
+        if (r.sync && ws->host_ctl->state != ST_CONVERGED && (ws->host_ctl->sweeps & 1))
+            CONTOUR_HIP(hipMemcpyAsync(L, other, sizeof(int) * (size_t)n, hipMemcpyDeviceToDevice, stream));
     }
     if (ev_end) CONTOUR_HIP(hipEventRecord(ev_end, stream));
     if (stats) {
@@ -339,6 +293,24 @@ static int run_solve(const int* src, const int* dst, long long m, int n, int* L,
         CONTOUR_HIP(hipGetLastError());
     }
     return CONTOUR_OK;
+}
+
+static int run_solve(const int* src, const int* dst, long long m, int n, int* L, const Resolved& r,
+                     contour_stats_t* stats, hipStream_t stream)
+{
+    DeviceInfo d;
+    int rc = device_info(&d);
+    if (rc) return rc;
+    Workspace* ws = nullptr;
+    rc = workspace_for(stream, &ws);
+    if (rc) return rc;
+    if (r.driver == CONTOUR_DRIVER_HOSTLOOP) return run_hostloop(d, r, src, dst, m, n, L, ws, stats, stream);
+    PersistentLaunch p;
+    rc = prepare_persistent(d, r, src, dst, m, n, L, ws->ctl, &p);
+    if (rc) return rc;
+    hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+    timing_events(&ev_begin, &ev_end);
+    return enqueue_persistent(p, stats, stream, ev_begin, ev_end);
 }
 
 }  // namespace contour

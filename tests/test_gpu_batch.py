@@ -1,0 +1,174 @@
+"""GPU parity of the batched path: every graph of a CSR-of-graphs batch gets
+exactly its own minimum-id labels (local ids), identical to the CPU oracle and
+to a standalone solve of that graph, whatever the batch around it."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def contour():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2311_02811_amd as contour
+    contour.load()
+    return contour
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
+
+
+def banner(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    # sizes spread so that all three classes appear with the tuning below
+    b = graphgen.batch(400, 5, median=400, sigma=1.6, n_lo=1, n_hi=300000)
+    exp = oracle.uf_batch(b.edge_off, b.vertex_off, b.src, b.dst)
+    return b, exp
+
+
+FORCE_CLASSES = dict(lds_max_vertices=1500, wg_max_edges=30000)
+
+
+def run_plan(contour, b, tuning=None, **opts):
+    s, d = dev(b.src), dev(b.dst)
+    plan = contour.BatchPlan(b.edge_off, b.vertex_off, s, d, tuning=tuning, **opts)
+    plan.launch()
+    torch.cuda.synchronize()
+    out = plan.labels.cpu().numpy(), plan.stats.cpu().numpy(), plan.classes()
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(order=1), dict(order=3), dict(order="full"),
+                                  dict(write="atomic"), dict(schedule="1m1m", order=1024)],
+                         ids=["default", "order1", "order3", "full", "atomic", "1m1m"])
+def test_batch_matches_oracle_all_classes(contour, small_batch, opts):
+    b, exp = small_batch
+    tuning = contour.make_tuning(**FORCE_CLASSES)
+    banner("batch G=%d classes forced %r" % (b.num_graphs, opts))
+    labels, stats, classes = run_plan(contour, b, tuning=tuning, **opts)
+    assert all(c > 0 for c in classes), classes
+    assert np.array_equal(labels, exp)
+    assert np.all(stats[:, 0] == 0)
+    assert np.all(stats[b.m > 0, 1] >= 1)
+
+
+def test_batch_tuned_geometries(contour, small_batch):
+    b, exp = small_batch
+    for spec in ([dict(block=256, edges_per_thread=1), dict(block=1024, edges_per_thread=4),
+                  dict(block=512, edges_per_thread=8)],
+                 [dict(block=1024, edges_per_thread=2, order=3), dict(block=256, edges_per_thread=1,
+                                                                      order="full"),
+                  dict(block=256, edges_per_thread=1, order=2)]):
+        tuning = contour.make_tuning(spec, **FORCE_CLASSES)
+        banner("batch tuned %r" % spec)
+        labels, stats, _ = run_plan(contour, b, tuning=tuning)
+        assert np.array_equal(labels, exp)
+
+
+def test_batch_slice_equals_standalone(contour, small_batch):
+    b, exp = small_batch
+    labels, _, _ = run_plan(contour, b, tuning=contour.make_tuning(**FORCE_CLASSES))
+    for g in range(0, b.num_graphs, 37):
+        s, d, n = b.graph(g)
+        v0 = int(b.vertex_off[g])
+        alone = contour.cc(dev(s), dev(d), n).cpu().numpy() if n else np.empty(0, np.int32)
+        assert np.array_equal(labels[v0:v0 + n], alone), g
+
+
+def test_batch_edge_cases(contour):
+    # empty graphs, edgeless graphs, a single vertex, duplicates and self-loops
+    graphs = [(0, []), (1, []), (3, []), (2, [(1, 0), (0, 1), (1, 1)]), (5, [(4, 3), (3, 2)]),
+              (70000, [(69999, 0)])]
+    src, dst, eo, vo = [], [], [0], [0]
+    for n, edges in graphs:
+        for a, c in edges:
+            src.append(a)
+            dst.append(c)
+        eo.append(len(src))
+        vo.append(vo[-1] + n)
+    src = np.array(src, np.int32)
+    dst = np.array(dst, np.int32)
+    exp = oracle.uf_batch(eo, vo, src, dst)
+    plan = contour.BatchPlan(eo, vo, dev(src), dev(dst))
+    plan.launch()
+    torch.cuda.synchronize()
+    assert np.array_equal(plan.labels.cpu().numpy(), exp)
+    st = plan.stats.cpu().numpy()
+    assert np.all(st[:, 0] == 0)
+    assert st[0, 1] == 0 and st[1, 1] == 0
+    plan.close()
+    # a batch with no graphs at all
+    e = torch.zeros(0, dtype=torch.int32, device="cuda")
+    plan = contour.BatchPlan([0], [0], e, e)
+    plan.launch()
+    torch.cuda.synchronize()
+    plan.close()
+
+
+def test_batch_out_of_range_local_id(contour):
+    src = np.array([0, 5, 1], np.int32)     # graph 1 has n = 3: id 5 is out of range
+    dst = np.array([1, 0, 2], np.int32)
+    eo, vo = [0, 1, 3], [0, 2, 5]
+    plan = contour.BatchPlan(eo, vo, dev(src), dev(dst))
+    plan.launch()
+    torch.cuda.synchronize()
+    st = plan.stats.cpu().numpy()
+    assert st[0, 0] == 0 and st[1, 0] == contour.ERANGE
+    assert np.array_equal(plan.labels.cpu().numpy(), [0, 0, 0, 1, 1])
+    plan.close()
+
+
+def test_plan_relaunch_and_graph_capture(contour, small_batch):
+    b, exp = small_batch
+    s, d = dev(b.src), dev(b.dst)
+    plan = contour.BatchPlan(b.edge_off, b.vertex_off, s, d,
+                             tuning=contour.make_tuning(**FORCE_CLASSES))
+    for _ in range(3):
+        plan.labels.fill_(-1)
+        plan.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(plan.labels.cpu().numpy(), exp)
+    # capture one launch into a graph and replay it, with eager work between
+    side = torch.cuda.Stream()
+    plan.launch(side)            # warm-up on a non-default stream before capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.launch()
+    for rep in range(4):
+        plan.labels.fill_(-1)
+        x = torch.arange(1000, device="cuda").sum()   # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(x) == 499500
+        banner("graph replay %d" % rep)
+        assert np.array_equal(plan.labels.cpu().numpy(), exp), rep
+    plan.close()
+
+
+def test_batched_config_full(contour):
+    banner("generating the 20,000-graph batch")
+    b = graphgen.batch(20000, 1)
+    exp = oracle.uf_batch(b.edge_off, b.vertex_off, b.src, b.dst)
+    s, d = dev(b.src), dev(b.dst)
+    plan = contour.BatchPlan(b.edge_off, b.vertex_off, s, d)
+    banner("classes %r" % plan.classes())
+    plan.launch()
+    torch.cuda.synchronize()
+    assert np.array_equal(plan.labels.cpu().numpy(), exp)
+    st = plan.stats.cpu().numpy()
+    assert np.all(st[:, 0] == 0)
+    print("batch sweeps: max %d mean %.2f" % (st[:, 1].max(), st[:, 1].mean()))
+    plan.close()
