@@ -129,6 +129,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall-clock budget for the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--reorder", default="auto", choices=["auto", "on", "off"])
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--edges-per-thread", type=int, default=0)
+    ap.add_argument("--chunk-tiles", type=int, default=0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized int32 buffer --steps times (HBM counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -143,11 +149,22 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_copy": nbytes, "copies": args.steps}))
+        return
     log("generating %s (seed %d)" % (args.workload, args.seed))
     src, dst, n = make_workload(args.workload, args.seed)
     m = int(src.size)
     order = order_value(args.order)
-    opts = dict(order=order, write=args.write, driver=args.driver)
+    opts = dict(order=order, write=args.write, driver=args.driver, reorder=args.reorder,
+                block=args.block, edges_per_thread=args.edges_per_thread,
+                chunk_tiles=args.chunk_tiles)
     log("timing %d steps after %d warm-up steps: n=%d m=%d %r" % (args.steps, args.warmup, n, m, opts))
     r = time_gpu(contour, torch, src, dst, n, args.steps, args.warmup, opts)
     ms_per_step = r["total_ms"] / args.steps
@@ -179,7 +196,9 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "seed": args.seed,
-                   "order": order, "write": args.write, "driver": args.driver},
+                   "order": order, "write": args.write, "driver": args.driver,
+                   "reorder": args.reorder, "block": args.block,
+                   "edges_per_thread": args.edges_per_thread, "chunk_tiles": args.chunk_tiles},
         "sweeps": {"min": min(sweeps), "max": max(sweeps), "mean": statistics.mean(sweeps)},
         "status": status,
         "edge_sweeps_per_s": round(statistics.mean(sweeps) * m / (kernel_ms / 1e3), 1),

@@ -100,12 +100,23 @@ typedef struct {
     int32_t max_sweeps;  /* 0 = no limit */
     int32_t warm_start;  /* 1: labels_inout holds a state with L[x] <= x and L[x] in x's
                             component (e.g. a partial result); 0: start from L[x] = x */
-    int32_t block;       /* threads per workgroup, 0 = auto (multiple of 64, <= 1024) */
+    int32_t block;       /* threads per workgroup, 0 = auto; 256, 512 or 1024 */
     int32_t edges_per_thread; /* 0 = auto; 1, 2, 4 or 8 */
     int32_t chunk_tiles; /* persistent driver: tiles (block * edges_per_thread edges)
                             per task, 0 = auto */
     int32_t grid;        /* workgroups, 0 = auto (all resident) */
+    int32_t reorder;     /* CONTOUR_REORDER_*: bucket the edges by source-vertex block
+                            before the sweeps (a counting sort on device) */
 } contour_opts_t;
+
+/* Edge reordering.  The sweeps may apply MM^h to the edges in any order
+ * (Section III-B-1 leaves the order of the asynchronous updates free), so the
+ * library may first copy the edge list into a workspace grouped by blocks of
+ * source ids: the label gathers of neighbouring edges then share cache lines.
+ * The input arrays are never modified; labels are identical either way. */
+#define CONTOUR_REORDER_AUTO 0 /* on when the label array exceeds the caches of one XCD */
+#define CONTOUR_REORDER_OFF 1
+#define CONTOUR_REORDER_ON 2
 
 typedef struct {
     int32_t status;             /* contour_status_t of the data checks */

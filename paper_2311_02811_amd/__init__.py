@@ -22,6 +22,7 @@ _SCHED = {"fixed": 0, "11mm": 1, "1m1m": 2}
 _WRITE = {"plain": 0, "atomic": 1}
 _UPDATE = {"async": 0, "sync": 1}
 _DRIVER = {"persistent": 0, "hostloop": 1}
+_REORDER = {"auto": 0, "off": 1, "on": 2}
 
 OK, EINVAL, ERANGE, ENOMEM, EHIP, ENOCONV, ENOTSUP = range(7)
 
@@ -70,7 +71,7 @@ def _check_edges(src, dst):
 
 def make_opts(order=2, schedule="fixed", k1=2, write="plain", update="async",
               driver="persistent", max_sweeps=0, warm_start=False, block=0,
-              edges_per_thread=0, chunk_tiles=0, grid=0) -> ContourOpts:
+              edges_per_thread=0, chunk_tiles=0, grid=0, reorder="auto") -> ContourOpts:
     o = ContourOpts()
     load().contour_default_opts(ctypes.byref(o))
     o.order = ORDER_FULL if order in ("full", ORDER_FULL) else int(order)
@@ -85,6 +86,7 @@ def make_opts(order=2, schedule="fixed", k1=2, write="plain", update="async",
     o.edges_per_thread = int(edges_per_thread)
     o.chunk_tiles = int(chunk_tiles)
     o.grid = int(grid)
+    o.reorder = _REORDER[reorder]
     return o
 
 

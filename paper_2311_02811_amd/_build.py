@@ -21,6 +21,7 @@ SOURCES = [
     "contour_runtime.cpp",
     "contour_single.hip",
     "contour_batch.hip",
+    "contour_reorder.hip",
 ]
 
 HIPCC_FLAGS = [

@@ -460,6 +460,7 @@ static int create_plan(const contour_batch_t* b, const contour_opts_t* opts, con
         rc2.block = block[2];
         rc2.ept = ept[2];
         rc2.grid = 0;
+        rc2.reorder = CONTOUR_REORDER_OFF;
         p->multi_kernel = pick_multi(block[2], ept[2], r.atomic);
         int occ = 0;
         if (e == hipSuccess)
@@ -471,7 +472,7 @@ static int create_plan(const contour_batch_t* b, const contour_opts_t* opts, con
             const int g = big[k];
             PersistentLaunch pl;
             int rr = prepare_persistent(d, rc2, b->src + eo[g], b->dst + eo[g], eo[g + 1] - eo[g],
-                                        (int)(vo[g + 1] - vo[g]), b->labels_out + vo[g], p->d_ctl + k, &pl);
+                                        (int)(vo[g + 1] - vo[g]), b->labels_out + vo[g], p->d_ctl + k, nullptr, &pl);
             if (rr) {
                 free_plan(p);
                 return rr;

@@ -17,9 +17,36 @@ namespace contour {
 // reads every store of sweeps < s.  Returns when the graph's solve has ended
 // (converged, sweep limit or watchdog); several workgroups may return for
 // the same graph.
+// Per-workgroup bookkeeping of the persistent loop (thread 0 only).
+// Completed tasks are published once per sweep: when the workgroup moves on
+// to a later sweep it first releases its stores (agent-scope release) and
+// adds its count to done_task, and only then may it wait for that sweep to
+// be complete.  A workgroup therefore issues one release, one done_task
+// add and one acquire per sweep it takes part in, instead of one per task.
+struct PersistentState {
+    long long sweep;    // sweep of the last task taken (-1: none yet)
+    int pending;        // tasks of that sweep completed but not yet published
+    int changed;        // some published-later task changed a label
+    int err;            // some task met an out-of-range id
+};
+
+__device__ __forceinline__ void persistent_publish(const SolveArgs& a, PersistentState& w)
+{
+    if (w.pending == 0) return;
+    Ctl* c = a.ctl;
+    if (w.changed)
+        __hip_atomic_fetch_max(&c->last_change, (int)w.sweep + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (w.err) __hip_atomic_store(&c->range_err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&c->done_task, (unsigned long long)w.pending, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    w.pending = 0;
+    w.changed = 0;
+    w.err = 0;
+}
+
 // Thread 0 only: take the next task of the graph and decide whether the
-// workgroup works on it.  Writes the decision to *go and the task to *task.
-__device__ __forceinline__ void persistent_next(const SolveArgs& a, int* go_out, long long* task_out)
+// workgroup works on it.
+__device__ __forceinline__ void persistent_next(const SolveArgs& a, PersistentState& w, int* go_out,
+                                                long long* task_out)
 {
     Ctl* c = a.ctl;
     int go = 0;
@@ -27,21 +54,26 @@ __device__ __forceinline__ void persistent_next(const SolveArgs& a, int* go_out,
     if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ST_RUNNING) {
         t = (long long)__hip_atomic_fetch_add(&c->next_task, 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const long long sweep = t / a.tasks;
-        if (sweep > 0) {
-            const unsigned long long need = (unsigned long long)(sweep * a.tasks);
-            while (__hip_atomic_load(&c->done_task, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ST_RUNNING)
-                    break;
-                if (watchdog_expired(c, a.watchdog)) {
-                    int expect = ST_RUNNING;
-                    __hip_atomic_compare_exchange_strong(&c->state, &expect, (int)ST_TIMEOUT, __ATOMIC_RELAXED,
-                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
+        if (sweep != w.sweep) {
+            // leaving w.sweep for good: publish it before waiting on sweep - 1
+            persistent_publish(a, w);
+            if (sweep > 0) {
+                const unsigned long long need = (unsigned long long)(sweep * a.tasks);
+                while (__hip_atomic_load(&c->done_task, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ST_RUNNING)
+                        break;
+                    if (watchdog_expired(c, a.watchdog)) {
+                        int expect = ST_RUNNING;
+                        __hip_atomic_compare_exchange_strong(&c->state, &expect, (int)ST_TIMEOUT, __ATOMIC_RELAXED,
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
                 }
-                __builtin_amdgcn_s_sleep(2);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
+            w.sweep = sweep;
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ST_RUNNING) {
             const int lc = __hip_atomic_load(&c->last_change, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             int st = ST_RUNNING;
@@ -65,25 +97,20 @@ __device__ __forceinline__ void persistent_next(const SolveArgs& a, int* go_out,
     *task_out = t;
 }
 
-// Thread 0 only: publish the end of a task (release).
-__device__ __forceinline__ void persistent_done(const SolveArgs& a, long long sweep, int any, int anyerr)
-{
-    Ctl* c = a.ctl;
-    if (any)
-        __hip_atomic_fetch_max(&c->last_change, (int)sweep + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (anyerr) __hip_atomic_store(&c->range_err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(&c->done_task, 1ULL, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // The loop keeps every thread-0 section inside one if-region at the end of
 // the body (plus one before the loop), so all lanes of every wave pass the
-// same barriers in the same order.
+// same barriers in the same order.  The convergence decision reads
+// last_change only after done_task shows every task of the previous sweep
+// published, and each publication adds to done_task with release semantics
+// after its last_change update, so a sweep that changed a label is never
+// mistaken for one that did not.
 template <int EPT, int BLOCK, bool ATOMIC>
 __device__ __forceinline__ void persistent_solve(const SolveArgs& a)
 {
     __shared__ long long s_task;
     __shared__ int s_go;
-    if (threadIdx.x == 0) persistent_next(a, &s_go, &s_task);
+    PersistentState w{-1, 0, 0, 0};
+    if (threadIdx.x == 0) persistent_next(a, w, &s_go, &s_task);
     __syncthreads();
     for (;;) {
         if (!uniform(s_go)) break;
@@ -98,8 +125,10 @@ __device__ __forceinline__ void persistent_solve(const SolveArgs& a)
         const int any = __syncthreads_or(pred ? 1 : 0);
         const int anyerr = __syncthreads_or(rerr);
         if (threadIdx.x == 0) {
-            persistent_done(a, sweep, any, anyerr);
-            persistent_next(a, &s_go, &s_task);
+            w.pending += 1;
+            w.changed |= any;
+            w.err |= anyerr;
+            persistent_next(a, w, &s_go, &s_task);
         }
         __syncthreads();
     }

@@ -119,11 +119,12 @@ int resolve_opts(const contour_opts_t* o, Resolved* r)
     if (o->update != CONTOUR_UPDATE_ASYNC && o->update != CONTOUR_UPDATE_SYNC) return CONTOUR_EINVAL;
     if (o->driver != CONTOUR_DRIVER_PERSISTENT && o->driver != CONTOUR_DRIVER_HOSTLOOP)
         return CONTOUR_EINVAL;
-    if (o->block != 0 && o->block != 256 && o->block != 512) return CONTOUR_EINVAL;
+    if (o->block != 0 && o->block != 256 && o->block != 512 && o->block != 1024) return CONTOUR_EINVAL;
     if (o->edges_per_thread != 0 && o->edges_per_thread != 1 && o->edges_per_thread != 2 &&
         o->edges_per_thread != 4 && o->edges_per_thread != 8)
         return CONTOUR_EINVAL;
     if (o->chunk_tiles < 0 || o->grid < 0) return CONTOUR_EINVAL;
+    if (o->reorder < CONTOUR_REORDER_AUTO || o->reorder > CONTOUR_REORDER_ON) return CONTOUR_EINVAL;
     // Algorithm 1 applies its conditional assignments to L_u with the
     // compare-and-swap loop of Eq. (cas); the synchronous update is only
     // offered that way, and sequenced from the host.
@@ -142,6 +143,7 @@ int resolve_opts(const contour_opts_t* o, Resolved* r)
     r->ept = o->edges_per_thread;
     r->chunk_tiles = o->chunk_tiles;
     r->grid = o->grid;
+    r->reorder = o->reorder;
     return CONTOUR_OK;
 }
 
@@ -164,6 +166,7 @@ void contour_default_opts(contour_opts_t* opts)
     opts->edges_per_thread = 0;
     opts->chunk_tiles = 0;
     opts->grid = 0;
+    opts->reorder = CONTOUR_REORDER_AUTO;
 }
 
 const char* contour_status_string(int s)

@@ -61,6 +61,7 @@ struct Resolved {
     int ept;
     int chunk_tiles;
     int grid;
+    int reorder;
 };
 
 // Wall-clock ticks a single solve may run before the watchdog stops it
@@ -69,6 +70,30 @@ unsigned long long watchdog_ticks(const DeviceInfo& d);
 
 // Per-thread timing events set by contour_set_timing_events (may be null).
 void timing_events(hipEvent_t* begin, hipEvent_t* end);
+
+// Edge reordering by source block (contour_reorder.hip).
+struct Reorder {
+    int shift = 0;          // bucket = src >> shift
+    int K = 0;              // buckets
+    int G = 0;              // workgroups of the count and scatter passes
+    long long chunk = 0;    // edges per workgroup
+    int nblk = 0;           // scan blocks
+    long long m = 0;
+    long long elems = 0;    // workspace ints needed
+    int* src2 = nullptr;    // workspace: reordered edges
+    int* dst2 = nullptr;
+    int* counts = nullptr;  // workspace: K x G matrix
+    int* sums = nullptr;    // workspace: scan block totals
+};
+
+// Sizes for m edges over n > 0 vertices.
+void reorder_geometry(const DeviceInfo& d, long long m, int n, Reorder* r);
+// Point the reorder at a workspace of at least r->elems ints.
+void reorder_bind(Reorder* r, int* ws);
+// Enqueue the counting sort of (src, dst) into r.src2 / r.dst2.
+int enqueue_reorder(const Reorder& r, const int* src, const int* dst, hipStream_t stream);
+// Whether the automatic policy reorders a graph of this size.
+inline bool reorder_auto(long long m, int n) { return n > (1 << 20) && m >= (1 << 20); }
 
 // A prepared single-graph persistent solve: everything needed to enqueue it
 // without allocating (used by contour_cc_ex and by batched plans).
@@ -80,11 +105,17 @@ struct PersistentLaunch {
     unsigned init_blocks;
     int warm;
     int n;
+    bool reorder;
+    Reorder ro;
+    const int* src_in;  // caller's edges (read by the reorder)
+    const int* dst_in;
 };
 
 // Resolve geometry and fill *out for a solve that uses control block `ctl`.
+// When the options ask for reordering, `ws` must hold reorder elems ints
+// (see reorder_geometry) and the sweeps read the reordered copy.
 int prepare_persistent(const DeviceInfo& d, const Resolved& r, const int* src, const int* dst,
-                       long long m, int n, int* L, Ctl* ctl, PersistentLaunch* out);
+                       long long m, int n, int* L, Ctl* ctl, int* ws, PersistentLaunch* out);
 
 // Enqueue: reset the control block, initialise (or check) labels, run the
 // persistent sweep kernel, write stats.  Optional events bracket the sweeps.

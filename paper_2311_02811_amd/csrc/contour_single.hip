@@ -119,6 +119,8 @@ __global__ void k_copy_labels(const int* R, int* W, unsigned n, const Ctl* c)
 typedef void (*persistent_fn)(SolveArgs);
 typedef void (*sweep_fn)(SolveArgs, const int*, int*, int);
 
+// 1024-thread workgroups get at most 128 registers per lane, which eight
+// edges per thread of the persistent loop exceed: they use four.
 template <int BLOCK, bool ATOMIC>
 static void pick(int ept, persistent_fn* p, sweep_fn* s)
 {
@@ -126,13 +128,19 @@ static void pick(int ept, persistent_fn* p, sweep_fn* s)
     case 1: *p = k_persistent<1, BLOCK, ATOMIC>; *s = k_sweep<1, BLOCK, ATOMIC>; break;
     case 2: *p = k_persistent<2, BLOCK, ATOMIC>; *s = k_sweep<2, BLOCK, ATOMIC>; break;
     case 4: *p = k_persistent<4, BLOCK, ATOMIC>; *s = k_sweep<4, BLOCK, ATOMIC>; break;
-    default: *p = k_persistent<8, BLOCK, ATOMIC>; *s = k_sweep<8, BLOCK, ATOMIC>; break;
+    default:
+        *p = BLOCK == 1024 ? k_persistent<4, BLOCK, ATOMIC> : k_persistent<8, BLOCK, ATOMIC>;
+        *s = k_sweep<8, BLOCK, ATOMIC>;
+        break;
     }
 }
 
 static void pick_kernels(int block, int ept, bool atomic, persistent_fn* p, sweep_fn* s)
 {
-    if (block == 512) {
+    if (block == 1024) {
+        if (atomic) pick<1024, true>(ept, p, s);
+        else pick<1024, false>(ept, p, s);
+    } else if (block == 512) {
         if (atomic) pick<512, true>(ept, p, s);
         else pick<512, false>(ept, p, s);
     } else {
@@ -141,24 +149,54 @@ static void pick_kernels(int block, int ept, bool atomic, persistent_fn* p, swee
     }
 }
 
+static bool wants_reorder(const Resolved& r, long long m, int n)
+{
+    if (m >= 0x7fffffffLL) return false;  // slots of the counting sort are int32
+    if (r.reorder == CONTOUR_REORDER_ON) return true;
+    if (r.reorder == CONTOUR_REORDER_OFF) return false;
+    return reorder_auto(m, n);
+}
+
 // Geometry: 256-thread workgroups; edges per thread grow with m so that small
 // graphs still spread over many workgroups and large ones get memory-level
 // parallelism; persistent tasks aim at several tasks per workgroup and sweep.
+// Geometry.  Large graphs: 1024-thread workgroups (one per CU) with four
+// edges per thread.  Small graphs: 256-thread workgroups and one or two
+// edges per thread, so that the edges still spread over many workgroups.
 static void auto_geometry(const DeviceInfo& d, long long m, Resolved* r)
 {
-    if (r->block == 0) r->block = 256;
-    if (r->ept == 0) {
-        long long threads_full = (long long)d.cus * 2048;  // one edge per resident thread
-        r->ept = m <= threads_full ? 1 : (m <= 4 * threads_full ? 2 : 4);
-    }
+    (void)d;
+    const bool large = m >= (4LL << 20);
+    if (r->block == 0) r->block = large ? 1024 : 256;
+    if (r->ept == 0) r->ept = large ? 4 : (m >= (1LL << 20) ? 2 : 1);
+}
+
+// Persistent tasks: every task takes one counter increment, and every
+// workgroup publishes once per sweep, so tasks are large: m / 256 edges,
+// between 4096 and 65536 (measured best on the MI355X for graphs from 0.5 M
+// to 268 M edges).
+static int auto_tiles_per_task(long long m, long long tile_edges)
+{
+    const long long want = std::max<long long>(4096, std::min<long long>(65536, m / 256));
+    return (int)std::max<long long>(1, want / tile_edges);
 }
 
 int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, const int* dst,
-                       long long m, int n, int* L, Ctl* ctl, PersistentLaunch* out)
+                       long long m, int n, int* L, Ctl* ctl, int* ws, PersistentLaunch* out)
 {
     Resolved r = r0;
     auto_geometry(d, m, &r);
     PersistentLaunch p;
+    p.src_in = src;
+    p.dst_in = dst;
+    p.reorder = m > 0 && wants_reorder(r, m, n);
+    if (p.reorder) {
+        if (!ws) return CONTOUR_EINVAL;
+        reorder_geometry(d, m, n, &p.ro);
+        reorder_bind(&p.ro, ws);
+        src = p.ro.src2;
+        dst = p.ro.dst2;
+    }
     p.n = n;
     p.warm = r.warm ? 1 : 0;
     p.init_blocks = (unsigned)std::max<long long>(
@@ -186,11 +224,7 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
         int occ = 0;
         CONTOUR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)p.kernel, r.block, 0));
         const long long resident = (long long)std::max(occ, 1) * d.cus;
-        int tpt = r.chunk_tiles;
-        if (tpt == 0) {
-            // about 4 tasks per resident workgroup and sweep, at most 16 tiles each
-            tpt = (int)std::max<long long>(1, std::min<long long>(16, ntiles / (4 * resident)));
-        }
+        const int tpt = r.chunk_tiles ? r.chunk_tiles : auto_tiles_per_task(m, tile_edges);
         a.tiles_per_task = tpt;
         a.tasks = (ntiles + tpt - 1) / tpt;
         p.grid = (unsigned)(r.grid ? r.grid : std::min<long long>(resident, a.tasks));
@@ -203,6 +237,10 @@ int enqueue_persistent(const PersistentLaunch& p, contour_stats_t* stats, hipStr
                        hipEvent_t ev_begin, hipEvent_t ev_end)
 {
     Ctl* ctl = p.args.ctl;
+    if (p.reorder) {
+        int rc = enqueue_reorder(p.ro, p.src_in, p.dst_in, stream);
+        if (rc) return rc;
+    }
     hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, stream, ctl);
     hipLaunchKernelGGL(k_init_labels, dim3(p.init_blocks), dim3(256), 0, stream, p.args.L,
                        (unsigned)p.n, p.warm, ctl);
@@ -241,6 +279,24 @@ static int run_hostloop(const DeviceInfo& d, const Resolved& r0, const int* src,
         persistent_fn kp;
         sweep_fn ks;
         pick_kernels(r.block, r.ept, r.atomic || r.sync, &kp, &ks);
+        const bool reorder = wants_reorder(r, m, n);
+        Reorder ro;
+        long long need = r.sync ? n : 0;
+        if (reorder) {
+            reorder_geometry(d, m, n, &ro);
+            need += ro.elems;
+        }
+        if (need > 0) {
+            int rc = workspace_scratch(ws, stream, need);
+            if (rc) return rc;
+        }
+        if (reorder) {
+            reorder_bind(&ro, ws->scratch);
+            int rc = enqueue_reorder(ro, src, dst, stream);
+            if (rc) return rc;
+            src = ro.src2;
+            dst = ro.dst2;
+        }
         SolveArgs a;
         a.src = src;
         a.dst = dst;
@@ -256,12 +312,7 @@ static int run_hostloop(const DeviceInfo& d, const Resolved& r0, const int* src,
         a.tiles_per_task = 1;
         a.tasks = ntiles;
         const long long grid = r.grid ? r.grid : std::min<long long>(ntiles, (long long)d.cus * 16);
-        int* other = nullptr;
-        if (r.sync) {
-            int rc = workspace_scratch(ws, stream, n);
-            if (rc) return rc;
-            other = ws->scratch;
-        }
+        int* other = r.sync ? ws->scratch + (reorder ? ro.elems : 0) : nullptr;
         int sweep = 0, ahead = 4;
         for (;;) {
             for (int i = 0; i < ahead; ++i, ++sweep) {
@@ -305,8 +356,16 @@ static int run_solve(const int* src, const int* dst, long long m, int n, int* L,
     rc = workspace_for(stream, &ws);
     if (rc) return rc;
     if (r.driver == CONTOUR_DRIVER_HOSTLOOP) return run_hostloop(d, r, src, dst, m, n, L, ws, stats, stream);
+    int* scratch = nullptr;
+    if (m > 0 && wants_reorder(r, m, n)) {
+        Reorder ro;
+        reorder_geometry(d, m, n, &ro);
+        rc = workspace_scratch(ws, stream, ro.elems);
+        if (rc) return rc;
+        scratch = ws->scratch;
+    }
     PersistentLaunch p;
-    rc = prepare_persistent(d, r, src, dst, m, n, L, ws->ctl, &p);
+    rc = prepare_persistent(d, r, src, dst, m, n, L, ws->ctl, scratch, &p);
     if (rc) return rc;
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;
     timing_events(&ev_begin, &ev_end);

@@ -62,6 +62,10 @@ MODES = [
     dict(driver="hostloop", update="sync", write="atomic"),
     dict(driver="hostloop", update="sync", write="atomic", order=1),
     dict(driver="hostloop", update="sync", write="atomic", order="full"),
+    dict(reorder="on"),
+    dict(reorder="on", order="full"),
+    dict(reorder="on", driver="hostloop"),
+    dict(reorder="on", driver="hostloop", update="sync", write="atomic"),
 ]
 MODE_IDS = ["-".join("%s=%s" % kv for kv in sorted(m.items())) or "default" for m in MODES]
 
@@ -200,10 +204,22 @@ def test_edge_cases(contour):
     assert np.array_equal(got, exp)
 
 
+def test_reorder_leaves_inputs_untouched(contour):
+    src, dst = graphgen.rmat(16, 8, 3)
+    n = 1 << 16
+    exp = oracle.uf_labels(src, dst, n)
+    s, d = dev(src), dev(dst)
+    for mode in (dict(reorder="on"), dict(reorder="on", driver="hostloop"), dict(reorder="off")):
+        lab, _ = contour.cc_ex(s, d, n, **mode)
+        assert np.array_equal(lab.cpu().numpy(), exp)
+        assert np.array_equal(s.cpu().numpy(), src) and np.array_equal(d.cpu().numpy(), dst)
+
+
 def test_out_of_range_ids_are_skipped_and_reported(contour):
     src = np.array([0, 1, 5, -1, 2], np.int32)
     dst = np.array([1, 2, 0, 3, 3], np.int32)
-    for mode in (dict(), dict(driver="hostloop"), dict(order="full")):
+    for mode in (dict(), dict(driver="hostloop"), dict(order="full"), dict(reorder="on"),
+                 dict(reorder="on", driver="hostloop")):
         got, st = solve(contour, src, dst, 5, **mode)
         assert st.status == contour.ERANGE
         # the graph without the bad edges: {0, 1, 2, 3}, {4}
@@ -300,7 +316,7 @@ def test_config_grid_full(contour):
     ncomp = int(np.count_nonzero(exp == np.arange(n)))
     s, d = dev(src), dev(dst)
     for mode in (dict(), dict(order=3), dict(order="full"), dict(write="atomic"),
-                 dict(driver="hostloop")):
+                 dict(driver="hostloop"), dict(reorder="off"), dict(reorder="on", order=1)):
         banner("grid full %r" % mode)
         lab, st = contour.cc_ex(s, d, n, **mode)
         got = lab.cpu().numpy()
@@ -317,7 +333,7 @@ def test_config_rmat_full(contour):
     exp = oracle.uf_labels(src, dst, n)
     s, d = dev(src), dev(dst)
     del src, dst
-    for mode in (dict(), dict(order=3), dict(order="full")):
+    for mode in (dict(), dict(order=3), dict(order="full"), dict(reorder="off")):
         banner("rmat full %r" % mode)
         lab, st = contour.cc_ex(s, d, n, **mode)
         assert np.array_equal(lab.cpu().numpy(), exp), mode
