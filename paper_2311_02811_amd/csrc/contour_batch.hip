@@ -219,13 +219,15 @@ __global__ void k_batch_multi_stats(const SolveArgs* graphs, const int* gidx, in
 typedef void (*wg_fn)(WgArgs);
 typedef void (*multi_fn)(const SolveArgs*, int, int*, const int*);
 
+// 1024-thread workgroups with labels in global memory would spill registers
+// at four edges per thread; they use two.
 template <int BLOCK, bool ATOMIC, bool LDS>
 static wg_fn pick_wg_e(int ept)
 {
     switch (ept) {
     case 1: return k_batch_wg<1, BLOCK, ATOMIC, LDS>;
     case 2: return k_batch_wg<2, BLOCK, ATOMIC, LDS>;
-    default: return k_batch_wg<4, BLOCK, ATOMIC, LDS>;
+    default: return k_batch_wg<(BLOCK == 1024 && !LDS) ? 2 : 4, BLOCK, ATOMIC, LDS>;
     }
 }
 

@@ -73,6 +73,9 @@ struct SolveArgs {
     int max_sweeps;      // 0 = no limit
     Ctl* ctl;
     unsigned long long watchdog;  // wall-clock ticks a solve may run, 0 = unbounded
+    int win_cap;         // LDS window capacity in labels (0: no window)
+    int win_shift;       // edges are grouped by src >> win_shift
+    int win_margin;      // labels staged past the last source block of a task
 };
 
 // Edge ids are streamed once per sweep: non-temporal loads keep them from
@@ -100,13 +103,13 @@ __device__ __forceinline__ void put(int* L, int x, int z)
 // ---------------------------------------------------------------------------
 
 template <int EPT, int BLOCK>
-__device__ __forceinline__ void load_tile(const int* __restrict__ src, const int* __restrict__ dst,
-                                          long long base, long long m, unsigned n, int (&w)[EPT],
-                                          int (&v)[EPT], bool (&ok)[EPT], int& rerr)
+__device__ __forceinline__ void fetch_tile(const int* __restrict__ src, const int* __restrict__ dst,
+                                           long long base, long long m, int (&w)[EPT], int (&v)[EPT],
+                                           bool (&ok)[EPT])
 {
-    // Loads are unconditional (an edge past the end re-reads edge m-1, an
-    // invalid edge gathers label 0) so that every load of the tile is in
-    // flight at once instead of each waiting behind a branch.
+    // Loads are unconditional (an edge past the end re-reads edge m-1) so
+    // that every load of the tile is in flight at once instead of each
+    // waiting behind a branch.
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
         const long long e = base + (long long)k * BLOCK + threadIdx.x;
@@ -115,6 +118,13 @@ __device__ __forceinline__ void load_tile(const int* __restrict__ src, const int
         w[k] = ld_edge(src + ec);
         v[k] = ld_edge(dst + ec);
     }
+}
+
+// Range check: an edge with an id outside [0, n) is flagged and skipped (it
+// then gathers label 0 and stores nothing).
+template <int EPT>
+__device__ __forceinline__ void check_tile(unsigned n, int (&w)[EPT], int (&v)[EPT], bool (&ok)[EPT], int& rerr)
+{
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
         const bool inr = (unsigned)w[k] < n && (unsigned)v[k] < n;
@@ -126,15 +136,15 @@ __device__ __forceinline__ void load_tile(const int* __restrict__ src, const int
 }
 
 // MM^1: z = min(L[w], L[v]); targets w, v.
-template <int EPT, bool ATOMIC>
-__device__ __forceinline__ bool tile_order1(const int* R, int* W, const int (&w)[EPT],
+template <int EPT, bool ATOMIC, class LAB>
+__device__ __forceinline__ bool tile_order1(const LAB& lab, const int (&w)[EPT],
                                             const int (&v)[EPT], const bool (&ok)[EPT])
 {
     int a[EPT], b[EPT];
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-        a[k] = R[w[k]];
-        b[k] = R[v[k]];
+        a[k] = lab.ld(w[k]);
+        b[k] = lab.ld(v[k]);
     }
     bool pred = false;
 #pragma unroll
@@ -142,27 +152,27 @@ __device__ __forceinline__ bool tile_order1(const int* R, int* W, const int (&w)
         const int z = min(a[k], b[k]);
         const bool act = ok[k] && max(a[k], b[k]) > z;
         pred |= act;
-        if (act && a[k] > z) put<ATOMIC>(W, w[k], z);
-        if (act && b[k] > z) put<ATOMIC>(W, v[k], z);
+        if (act && a[k] > z) lab.template st<ATOMIC>(w[k], z);
+        if (act && b[k] > z) lab.template st<ATOMIC>(v[k], z);
     }
     return pred;
 }
 
 // MM^2: z = min(L[L[w]], L[L[v]]); targets w, v, L[w], L[v].
-template <int EPT, bool ATOMIC>
-__device__ __forceinline__ bool tile_order2(const int* R, int* W, const int (&w)[EPT],
+template <int EPT, bool ATOMIC, class LAB>
+__device__ __forceinline__ bool tile_order2(const LAB& lab, const int (&w)[EPT],
                                             const int (&v)[EPT], const bool (&ok)[EPT])
 {
     int a[EPT], b[EPT], a2[EPT], b2[EPT];
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-        a[k] = R[w[k]];
-        b[k] = R[v[k]];
+        a[k] = lab.ld(w[k]);
+        b[k] = lab.ld(v[k]);
     }
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-        a2[k] = R[a[k]];
-        b2[k] = R[b[k]];
+        a2[k] = lab.ld(a[k]);
+        b2[k] = lab.ld(b[k]);
     }
     bool pred = false;
 #pragma unroll
@@ -170,34 +180,34 @@ __device__ __forceinline__ bool tile_order2(const int* R, int* W, const int (&w)
         const int z = min(a2[k], b2[k]);
         const bool act = ok[k] && max(a[k], b[k]) > z;
         pred |= act;
-        if (act && a[k] > z) put<ATOMIC>(W, w[k], z);
-        if (act && a2[k] > z) put<ATOMIC>(W, a[k], z);
-        if (act && b[k] > z) put<ATOMIC>(W, v[k], z);
-        if (act && b2[k] > z) put<ATOMIC>(W, b[k], z);
+        if (act && a[k] > z) lab.template st<ATOMIC>(w[k], z);
+        if (act && a2[k] > z) lab.template st<ATOMIC>(a[k], z);
+        if (act && b[k] > z) lab.template st<ATOMIC>(v[k], z);
+        if (act && b2[k] > z) lab.template st<ATOMIC>(b[k], z);
     }
     return pred;
 }
 
 // MM^3: z = min(L^3[w], L^3[v]); targets w, L[w], L^2[w] and the same for v.
-template <int EPT, bool ATOMIC>
-__device__ __forceinline__ bool tile_order3(const int* R, int* W, const int (&w)[EPT],
+template <int EPT, bool ATOMIC, class LAB>
+__device__ __forceinline__ bool tile_order3(const LAB& lab, const int (&w)[EPT],
                                             const int (&v)[EPT], const bool (&ok)[EPT])
 {
     int a[EPT], b[EPT], a2[EPT], b2[EPT], a3[EPT], b3[EPT];
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-        a[k] = R[w[k]];
-        b[k] = R[v[k]];
+        a[k] = lab.ld(w[k]);
+        b[k] = lab.ld(v[k]);
     }
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-        a2[k] = R[a[k]];
-        b2[k] = R[b[k]];
+        a2[k] = lab.ld(a[k]);
+        b2[k] = lab.ld(b[k]);
     }
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-        a3[k] = R[a2[k]];
-        b3[k] = R[b2[k]];
+        a3[k] = lab.ld(a2[k]);
+        b3[k] = lab.ld(b2[k]);
     }
     bool pred = false;
 #pragma unroll
@@ -205,12 +215,12 @@ __device__ __forceinline__ bool tile_order3(const int* R, int* W, const int (&w)
         const int z = min(a3[k], b3[k]);
         const bool act = ok[k] && max(a[k], b[k]) > z;
         pred |= act;
-        if (act && a[k] > z) put<ATOMIC>(W, w[k], z);
-        if (act && a2[k] > z) put<ATOMIC>(W, a[k], z);
-        if (act && a3[k] > z) put<ATOMIC>(W, a2[k], z);
-        if (act && b[k] > z) put<ATOMIC>(W, v[k], z);
-        if (act && b2[k] > z) put<ATOMIC>(W, b[k], z);
-        if (act && b3[k] > z) put<ATOMIC>(W, b2[k], z);
+        if (act && a[k] > z) lab.template st<ATOMIC>(w[k], z);
+        if (act && a2[k] > z) lab.template st<ATOMIC>(a[k], z);
+        if (act && a3[k] > z) lab.template st<ATOMIC>(a2[k], z);
+        if (act && b[k] > z) lab.template st<ATOMIC>(v[k], z);
+        if (act && b2[k] > z) lab.template st<ATOMIC>(b[k], z);
+        if (act && b3[k] > z) lab.template st<ATOMIC>(b2[k], z);
     }
     return pred;
 }
@@ -224,8 +234,8 @@ __device__ __forceinline__ bool tile_order3(const int* R, int* W, const int (&w)
 // chain; any value it reads is a valid label, and if its reads differ from
 // the first walk's, some other edge stored in this sweep, so a sweep that
 // reports a change always makes one.
-template <int EPT, bool ATOMIC>
-__device__ __forceinline__ bool tile_orderh(const int* R, int* W, const int (&w)[EPT],
+template <int EPT, bool ATOMIC, class LAB>
+__device__ __forceinline__ bool tile_orderh(const LAB& lab, const int (&w)[EPT],
                                             const int (&v)[EPT], const bool (&ok)[EPT], int h)
 {
     int cw[EPT], cv[EPT], fw[EPT], fv[EPT];
@@ -244,8 +254,8 @@ __device__ __forceinline__ bool tile_orderh(const int* R, int* W, const int (&w)
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
             int nw = cw[k], nv = cv[k];
-            if (!dw[k]) nw = R[cw[k]];
-            if (!dv[k]) nv = R[cv[k]];
+            if (!dw[k]) nw = lab.ld(cw[k]);
+            if (!dv[k]) nv = lab.ld(cv[k]);
             if (lvl == 0) {
                 fw[k] = nw;
                 fv[k] = nv;
@@ -273,8 +283,8 @@ __device__ __forceinline__ bool tile_orderh(const int* R, int* W, const int (&w)
         for (int side = 0; side < 2; ++side) {
             int x = side ? v[k] : w[k];
             for (int lvl = 0; h < 0 || lvl < h; ++lvl) {
-                int val = R[x];
-                if (val > z) put<ATOMIC>(W, x, z);
+                int val = lab.ld(x);
+                if (val > z) lab.template st<ATOMIC>(x, z);
                 if (val <= z || val == x) break;
                 x = val;
             }
@@ -285,45 +295,110 @@ __device__ __forceinline__ bool tile_orderh(const int* R, int* W, const int (&w)
 
 // Apply MM^ORDER (ORDER 0: the run-time order h) to the tiles
 // [first, first + count) of the edge list, stopping at m.
-template <int ORDER, int EPT, int BLOCK, bool ATOMIC>
+template <int ORDER, int EPT, int BLOCK, bool ATOMIC, class LAB>
 __device__ __forceinline__ bool run_tiles(const int* __restrict__ src, const int* __restrict__ dst,
-                                          const int* R, int* W, long long first, long long count,
+                                          const LAB& lab, long long first, long long count,
                                           long long stride, long long m, unsigned n, int h, int& rerr)
 {
+    // The edges of tile i+1 are fetched before tile i is processed, so the
+    // edge stream's latency overlaps the label gathers of the current tile.
     const long long tile_edges = (long long)BLOCK * EPT;
     bool pred = false;
+    long long base = first * tile_edges;
+    if (count <= 0 || base >= m) return false;
+    int w[EPT], v[EPT], nw[EPT], nv[EPT];
+    bool ok[EPT], nok[EPT];
+    fetch_tile<EPT, BLOCK>(src, dst, base, m, w, v, ok);
     for (long long i = 0; i < count; ++i) {
-        const long long base = (first + i * stride) * tile_edges;
-        if (base >= m) break;
-        int w[EPT], v[EPT];
-        bool ok[EPT];
-        load_tile<EPT, BLOCK>(src, dst, base, m, n, w, v, ok, rerr);
-        if (ORDER == 1) pred |= tile_order1<EPT, ATOMIC>(R, W, w, v, ok);
-        else if (ORDER == 2) pred |= tile_order2<EPT, ATOMIC>(R, W, w, v, ok);
-        else if (ORDER == 3) pred |= tile_order3<EPT, ATOMIC>(R, W, w, v, ok);
-        else pred |= tile_orderh<EPT, ATOMIC>(R, W, w, v, ok, h);
+        const long long next = base + stride * tile_edges;
+        const bool more = i + 1 < count && next < m;
+        if (more) fetch_tile<EPT, BLOCK>(src, dst, next, m, nw, nv, nok);
+        check_tile<EPT>(n, w, v, ok, rerr);
+        if (ORDER == 1) pred |= tile_order1<EPT, ATOMIC>(lab, w, v, ok);
+        else if (ORDER == 2) pred |= tile_order2<EPT, ATOMIC>(lab, w, v, ok);
+        else if (ORDER == 3) pred |= tile_order3<EPT, ATOMIC>(lab, w, v, ok);
+        else pred |= tile_orderh<EPT, ATOMIC>(lab, w, v, ok, h);
+        if (!more) break;
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            w[k] = nw[k];
+            v[k] = nv[k];
+            ok[k] = nok[k];
+        }
+        base = next;
     }
     return pred;
 }
 
 // Tiles first, first + stride, ... (count of them) under the order h.
+template <int EPT, int BLOCK, bool ATOMIC, class LAB>
+__device__ __forceinline__ bool run_tiles_lab(const int* __restrict__ src, const int* __restrict__ dst,
+                                              const LAB& lab, long long first, long long count,
+                                              long long stride, long long m, unsigned n, int h, int& rerr)
+{
+    switch (h) {
+    case 1: return run_tiles<1, EPT, BLOCK, ATOMIC>(src, dst, lab, first, count, stride, m, n, h, rerr);
+    case 2: return run_tiles<2, EPT, BLOCK, ATOMIC>(src, dst, lab, first, count, stride, m, n, h, rerr);
+    case 3: return run_tiles<3, EPT, BLOCK, ATOMIC>(src, dst, lab, first, count, stride, m, n, h, rerr);
+    default:
+        // A chain strictly decreases until its root, so it has at most n
+        // vertices: chase-to-root is the order n operator, and the bound also
+        // caps every walk.
+        if (h < 0 || (unsigned)h > n) h = (int)n;
+        return run_tiles<0, EPT, BLOCK, ATOMIC>(src, dst, lab, first, count, stride, m, n, h, rerr);
+    }
+}
+
+// Labels read from R and written to W, both in global memory (or both the
+// same LDS array for a graph solved inside one workgroup).
+struct FlatLabels {
+    const int* R;
+    int* W;
+    __device__ __forceinline__ int ld(int x) const { return R[x]; }
+    template <bool ATOMIC>
+    __device__ __forceinline__ void st(int x, int z) const { put<ATOMIC>(W, x, z); }
+};
+
+// A window of the label array, ids [lo, lo + cnt), staged in LDS; ids
+// outside it are read and written in global memory G.  Stores into the
+// window mark a dirty bit, and the workgroup writes the dirty labels back
+// once at the end of its task.
+struct WindowLabels {
+    int* lds;
+    unsigned* dirty;
+    unsigned lo;
+    unsigned cnt;
+    int* G;
+    __device__ __forceinline__ int ld(int x) const
+    {
+        const unsigned i = (unsigned)x - lo;
+        if (i < cnt) return lds[i];
+        return G[x];
+    }
+    template <bool ATOMIC>
+    __device__ __forceinline__ void st(int x, int z) const
+    {
+        const unsigned i = (unsigned)x - lo;
+        if (i < cnt) {
+            if (ATOMIC)
+                atomicMin(&lds[i], z);
+            else
+                lds[i] = z;
+            atomicOr(&dirty[i >> 5], 1u << (i & 31));
+        } else {
+            put<ATOMIC>(G, x, z);
+        }
+    }
+};
+
 template <int EPT, int BLOCK, bool ATOMIC>
 __device__ __forceinline__ bool run_tiles_order(const int* __restrict__ src, const int* __restrict__ dst,
                                                 const int* R, int* W, long long first, long long count,
                                                 long long stride, long long m, unsigned n, int h,
                                                 int& rerr)
 {
-    switch (h) {
-    case 1: return run_tiles<1, EPT, BLOCK, ATOMIC>(src, dst, R, W, first, count, stride, m, n, h, rerr);
-    case 2: return run_tiles<2, EPT, BLOCK, ATOMIC>(src, dst, R, W, first, count, stride, m, n, h, rerr);
-    case 3: return run_tiles<3, EPT, BLOCK, ATOMIC>(src, dst, R, W, first, count, stride, m, n, h, rerr);
-    default:
-        // A chain strictly decreases until its root, so it has at most n
-        // vertices: chase-to-root is the order n operator, and the bound also
-        // caps every walk.
-        if (h < 0 || (unsigned)h > n) h = (int)n;
-        return run_tiles<0, EPT, BLOCK, ATOMIC>(src, dst, R, W, first, count, stride, m, n, h, rerr);
-    }
+    const FlatLabels lab{R, W};
+    return run_tiles_lab<EPT, BLOCK, ATOMIC>(src, dst, lab, first, count, stride, m, n, h, rerr);
 }
 
 // Loop control read back from shared memory must be visibly uniform: the

@@ -2,6 +2,8 @@
 // the single-graph persistent kernel and the batched multi-workgroup kernel.
 #pragma once
 
+#include <algorithm>
+
 #include "contour_device.hpp"
 
 namespace contour {
@@ -104,7 +106,48 @@ __device__ __forceinline__ void persistent_next(const SolveArgs& a, PersistentSt
 // published, and each publication adds to done_task with release semantics
 // after its last_change update, so a sweep that changed a label is never
 // mistaken for one that did not.
+// Windowed task (edges grouped by source block): stage the labels of the
+// task's source blocks, plus a margin, in LDS; gather and store there for
+// ids inside the window and in global memory otherwise; write the labels the
+// task lowered back to global memory once at the end.  Stores into global
+// memory follow the write mode (plain or atomic minimum); values staged in
+// LDS were read during the sweep, so every label written back is smaller
+// than a value the location held during the sweep, exactly as for a direct
+// store.
 template <int EPT, int BLOCK, bool ATOMIC>
+__device__ __forceinline__ bool window_task(const SolveArgs& a, long long first_tile, int order, int& rerr)
+{
+    extern __shared__ int dyn_lds[];
+    __shared__ unsigned s_lo, s_cnt;
+    const long long tile_edges = (long long)BLOCK * EPT;
+    if (threadIdx.x == 0) {
+        const long long e0 = first_tile * tile_edges;
+        const long long e1 = std::min(a.m, e0 + (long long)a.tiles_per_task * tile_edges) - 1;
+        const unsigned f = (unsigned)a.src[e0], l = (unsigned)a.src[e1];
+        const unsigned lo = f < a.n ? (f >> a.win_shift) << a.win_shift : 0u;
+        unsigned long long hi = l < a.n ? ((unsigned long long)((l >> a.win_shift) + 1) << a.win_shift) : a.n;
+        hi = std::min<unsigned long long>(a.n, hi + (unsigned)a.win_margin);
+        s_lo = lo;
+        s_cnt = (unsigned)std::min<unsigned long long>(hi > lo ? hi - lo : 0ULL, (unsigned)a.win_cap);
+    }
+    __syncthreads();
+    const unsigned lo = uniform((int)s_lo);
+    const unsigned cnt = uniform((int)s_cnt);
+    int* wl = dyn_lds;
+    unsigned* dirty = reinterpret_cast<unsigned*>(dyn_lds + a.win_cap);
+    for (unsigned i = threadIdx.x; i < cnt; i += BLOCK) wl[i] = a.L[lo + i];
+    for (unsigned i = threadIdx.x; i < (cnt + 31) / 32; i += BLOCK) dirty[i] = 0;
+    __syncthreads();
+    const WindowLabels lab{wl, dirty, lo, cnt, a.L};
+    const bool pred = run_tiles_lab<EPT, BLOCK, ATOMIC>(a.src, a.dst, lab, first_tile, a.tiles_per_task, 1, a.m,
+                                                        a.n, order, rerr);
+    __syncthreads();
+    for (unsigned i = threadIdx.x; i < cnt; i += BLOCK)
+        if ((dirty[i >> 5] >> (i & 31)) & 1u) put<ATOMIC>(a.L, (int)(lo + i), wl[i]);
+    return pred;
+}
+
+template <int EPT, int BLOCK, bool ATOMIC, bool WIN = false>
 __device__ __forceinline__ void persistent_solve(const SolveArgs& a)
 {
     __shared__ long long s_task;
@@ -119,8 +162,12 @@ __device__ __forceinline__ void persistent_solve(const SolveArgs& a)
         const long long chunk = t - sweep * a.tasks;
         const int order = order_of_sweep(a.sched, (int)sweep);
         int rerr = 0;
-        const bool pred = run_tiles_order<EPT, BLOCK, ATOMIC>(a.src, a.dst, a.L, a.L, chunk * a.tiles_per_task,
-                                                              a.tiles_per_task, 1, a.m, a.n, order, rerr);
+        bool pred;
+        if (WIN)
+            pred = window_task<EPT, BLOCK, ATOMIC>(a, chunk * a.tiles_per_task, order, rerr);
+        else
+            pred = run_tiles_order<EPT, BLOCK, ATOMIC>(a.src, a.dst, a.L, a.L, chunk * a.tiles_per_task,
+                                                       a.tiles_per_task, 1, a.m, a.n, order, rerr);
         drain_stores();
         const int any = __syncthreads_or(pred ? 1 : 0);
         const int anyerr = __syncthreads_or(rerr);

@@ -1,21 +1,24 @@
 // contour_reorder.hip -- group the edge list by blocks of source ids.
 //
 // The asynchronous sweep may take the edges in any order (Section III-B-1),
-// so a solve may work on a copy of the edge list that is grouped by
-// src >> shift into at most 1024 buckets.  Neighbouring edges of the copy
-// then gather labels from a narrow id range and share cache lines, instead
-// of every gather touching its own line of the label array.
+// so a solve may work on a copy of the edge list that is grouped by the
+// source block b = src >> shift (at most 1024 blocks).  Neighbouring edges of
+// the copy then gather labels from a narrow id range, which the sweep stages
+// in LDS.
 //
-// A counting sort, three kernels and a scan:
-//   count    workgroup g counts the bucket of every edge of its contiguous
-//            chunk into LDS and writes the counts to column g of a
-//            bucket-major matrix counts[b * G + g];
-//   scan     exclusive prefix sum of the matrix in that (bucket-major) order
-//            gives workgroup g the first slot of each of its buckets;
-//   scatter  workgroup g walks its chunk again and writes each edge at its
-//            bucket's next slot (an LDS cursor per bucket).
-// An id outside [0, n) goes to the last bucket unchanged; the sweep's own
-// range check then rejects it.
+// The grouping is a stable least-significant-digit radix partition of b in
+// 5-bit digits (two passes for 1024 blocks).  Each pass:
+//   count    workgroup g counts the digits of its chunk of 2048 edges into
+//            counts[d * G + g] (digit-major);
+//   scan     an exclusive prefix sum of that matrix gives workgroup g the
+//            first output slot of each digit;
+//   scatter  workgroup g loads its chunk into LDS, orders it by digit there
+//            (stable: each thread owns eight consecutive edges and a column
+//            of per-digit counters), and writes each digit's run to its
+//            slots.  A run holds 64 edges on average, so the stores are
+//            whole cache lines rather than scattered words.
+// An id outside [0, n) goes to the last block unchanged; the sweep's own
+// range check rejects it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,27 +28,47 @@
 namespace contour {
 
 static constexpr int kMaxBuckets = 1024;
+static constexpr int kDigitBits = 5;
+static constexpr int kDigits = 1 << kDigitBits;
+static constexpr int kRxThreads = 256;
+static constexpr int kRxPer = 8;
+static constexpr int kRxChunk = kRxThreads * kRxPer;  // 2048 edges per workgroup
 static constexpr int kScanThreads = 1024;
 static constexpr int kScanPerThread = 8;
 static constexpr long long kScanSegment = (long long)kScanThreads * kScanPerThread;
 
-__device__ __forceinline__ int bucket_of(int w, int shift, int K)
+// Chunk handled by workgroup `blk` of `G`.  Workgroups are dispatched to the
+// eight XCDs round-robin; this mapping gives each XCD a contiguous range of
+// chunks, so the pieces of a digit's output run written by neighbouring
+// chunks are mostly written through the same L2 and merge into whole lines.
+__device__ __forceinline__ long long chunk_of(unsigned blk, unsigned G)
 {
-    const unsigned b = (unsigned)w >> shift;
-    return b < (unsigned)K ? (int)b : K - 1;
+    const unsigned per = (G + 7) / 8;
+    const unsigned x = blk % 8, k = blk / 8;
+    const unsigned full = G - (per - 1) * 8;  // XCDs that get `per` chunks (the rest get per - 1)
+    const unsigned start = x < full ? x * per : full * per + (x - full) * (per - 1);
+    return (long long)(start + k);
 }
 
-__global__ __launch_bounds__(256) void k_bucket_count(const int* __restrict__ src, long long m, long long chunk,
-                                                      int shift, int K, int* __restrict__ counts)
+__device__ __forceinline__ int digit_of(int w, int shift, int K, int pass)
 {
-    __shared__ int h[kMaxBuckets];
-    for (int i = threadIdx.x; i < K; i += 256) h[i] = 0;
+    const unsigned b0 = (unsigned)w >> shift;
+    const unsigned b = b0 < (unsigned)K ? b0 : (unsigned)(K - 1);
+    return (int)((b >> (kDigitBits * pass)) & (kDigits - 1));
+}
+
+__global__ __launch_bounds__(kRxThreads) void k_rx_count(const int* __restrict__ src, long long m, int shift,
+                                                         int K, int pass, int* __restrict__ counts)
+{
+    __shared__ int h[kDigits];
+    if (threadIdx.x < kDigits) h[threadIdx.x] = 0;
     __syncthreads();
-    const long long e0 = (long long)blockIdx.x * chunk;
-    const long long e1 = std::min(m, e0 + chunk);
-    for (long long e = e0 + threadIdx.x; e < e1; e += 256) atomicAdd(&h[bucket_of(ld_edge(src + e), shift, K)], 1);
+    const long long c = chunk_of(blockIdx.x, gridDim.x);
+    const long long e0 = c * kRxChunk;
+    const int len = (int)std::min<long long>(kRxChunk, m - e0);
+    for (int i = threadIdx.x; i < len; i += kRxThreads) atomicAdd(&h[digit_of(ld_edge(src + e0 + i), shift, K, pass)], 1);
     __syncthreads();
-    for (int i = threadIdx.x; i < K; i += 256) counts[(long long)i * gridDim.x + blockIdx.x] = h[i];
+    if (threadIdx.x < kDigits) counts[(long long)threadIdx.x * gridDim.x + c] = h[threadIdx.x];
 }
 
 // Exclusive scan, level 1: each block scans kScanSegment elements in place
@@ -82,7 +105,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_local(int* a, long long l
 // by a single block.
 __global__ __launch_bounds__(kScanThreads) void k_scan_sums(int* sums, int nblk)
 {
-    __shared__ int scratch_sums[kScanThreads];
+    __shared__ int tot[kScanThreads];
     const long long base = (long long)threadIdx.x * kScanPerThread;
     int v[kScanPerThread];
     int s = 0;
@@ -91,15 +114,15 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_sums(int* sums, int nblk)
         v[k] = base + k < nblk ? sums[base + k] : 0;
         s += v[k];
     }
-    scratch_sums[threadIdx.x] = s;
+    tot[threadIdx.x] = s;
     __syncthreads();
     for (int off = 1; off < kScanThreads; off <<= 1) {
-        const int t = threadIdx.x >= (unsigned)off ? scratch_sums[threadIdx.x - off] : 0;
+        const int t = threadIdx.x >= (unsigned)off ? tot[threadIdx.x - off] : 0;
         __syncthreads();
-        scratch_sums[threadIdx.x] += t;
+        tot[threadIdx.x] += t;
         __syncthreads();
     }
-    int run = threadIdx.x ? scratch_sums[threadIdx.x - 1] : 0;
+    int run = threadIdx.x ? tot[threadIdx.x - 1] : 0;
 #pragma unroll
     for (int k = 0; k < kScanPerThread; ++k) {
         if (base + k < nblk) sums[base + k] = run;
@@ -115,56 +138,121 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(int* a, long long len
         if (base + i < len) a[base + i] += add;
 }
 
-__global__ __launch_bounds__(256) void k_bucket_scatter(const int* __restrict__ src, const int* __restrict__ dst,
-                                                        long long m, long long chunk, int shift, int K,
-                                                        const int* __restrict__ offsets, int* __restrict__ src2,
-                                                        int* __restrict__ dst2)
+__global__ __launch_bounds__(kRxThreads) void k_rx_scatter(const int* __restrict__ src, const int* __restrict__ dst,
+                                                           long long m, int shift, int K, int pass,
+                                                           const int* __restrict__ offsets, int* __restrict__ osrc,
+                                                           int* __restrict__ odst)
 {
-    __shared__ int cur[kMaxBuckets];
-    for (int i = threadIdx.x; i < K; i += 256) cur[i] = offsets[(long long)i * gridDim.x + blockIdx.x];
+    __shared__ int in_s[kRxChunk], in_d[kRxChunk];
+    __shared__ int cnt[kDigits * kRxThreads];  // cnt[d * threads + t]
+    __shared__ int tot[kRxThreads];
+    __shared__ int dstart[kDigits];
+    __shared__ long long gbase[kDigits];
+    const int t = threadIdx.x;
+    const long long c = chunk_of(blockIdx.x, gridDim.x);
+    const long long e0 = c * kRxChunk;
+    const int len = (int)std::min<long long>(kRxChunk, m - e0);
+    for (int i = t; i < len; i += kRxThreads) {
+        in_s[i] = ld_edge(src + e0 + i);
+        in_d[i] = ld_edge(dst + e0 + i);
+    }
+    for (int i = t; i < kDigits * kRxThreads; i += kRxThreads) cnt[i] = 0;
+    if (t < kDigits) gbase[t] = offsets[(long long)t * gridDim.x + c];
     __syncthreads();
-    const long long e0 = (long long)blockIdx.x * chunk;
-    const long long e1 = std::min(m, e0 + chunk);
-    for (long long e = e0 + threadIdx.x; e < e1; e += 256) {
-        const int w = ld_edge(src + e);
-        const int v = ld_edge(dst + e);
-        const int pos = atomicAdd(&cur[bucket_of(w, shift, K)], 1);
-        src2[pos] = w;
-        dst2[pos] = v;
+    // thread t owns edges [t * kRxPer, (t + 1) * kRxPer) of the chunk
+    int dig[kRxPer];
+#pragma unroll
+    for (int k = 0; k < kRxPer; ++k) {
+        const int i = t * kRxPer + k;
+        dig[k] = i < len ? digit_of(in_s[i], shift, K, pass) : -1;
+        if (dig[k] >= 0) cnt[dig[k] * kRxThreads + t] += 1;
+    }
+    __syncthreads();
+    // exclusive scan of cnt in digit-major order: thread t scans entries
+    // [t * 32, t * 32 + 32), then the thread totals are scanned
+    int run = 0;
+    for (int k = 0; k < kDigits; ++k) {
+        const int x = cnt[t * kDigits + k];
+        cnt[t * kDigits + k] = run;
+        run += x;
+    }
+    tot[t] = run;
+    __syncthreads();
+    for (int off = 1; off < kRxThreads; off <<= 1) {
+        const int x = t >= off ? tot[t - off] : 0;
+        __syncthreads();
+        tot[t] += x;
+        __syncthreads();
+    }
+    const int add = t ? tot[t - 1] : 0;
+    for (int k = 0; k < kDigits; ++k) cnt[t * kDigits + k] += add;
+    __syncthreads();
+    // cnt[d * threads + t] is now the chunk-local rank of thread t's first
+    // digit-d edge, and digit d's run starts at rank dstart[d].  Each thread
+    // writes its edges straight to their slots, in order (stable), moving
+    // only its own counters.
+    if (t < kDigits) dstart[t] = cnt[t * kRxThreads];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRxPer; ++k) {
+        const int i = t * kRxPer + k;
+        if (dig[k] >= 0) {
+            const int d = dig[k];
+            const int r = cnt[d * kRxThreads + t]++;
+            const long long idx = gbase[d] + (r - dstart[d]);
+            osrc[idx] = in_s[i];
+            odst[idx] = in_d[i];
+        }
     }
 }
 
 void reorder_geometry(const DeviceInfo& d, long long m, int n, Reorder* r)
 {
+    (void)d;
     int shift = 0;
     while (((unsigned)(n - 1) >> shift) >= (unsigned)kMaxBuckets) ++shift;
     r->shift = shift;
     r->K = (int)(((unsigned)(n - 1) >> shift) + 1);
-    r->G = (int)std::max<long long>(1, std::min<long long>((m + 4095) / 4096, (long long)d.cus * 4));
-    r->chunk = (m + r->G - 1) / r->G;
-    const long long cells = (long long)r->K * r->G;
+    int passes = 0;
+    while ((1 << (kDigitBits * passes)) < r->K) ++passes;
+    r->passes = std::max(passes, 1);
+    r->G = (int)((m + kRxChunk - 1) / kRxChunk);
+    r->chunk = kRxChunk;
+    const long long cells = (long long)kDigits * r->G;
     r->nblk = (int)((cells + kScanSegment - 1) / kScanSegment);
     r->m = m;
-    r->elems = 2 * m + cells + r->nblk;
+    r->elems = 4 * m + cells + r->nblk;
 }
 
 void reorder_bind(Reorder* r, int* ws)
 {
     r->src2 = ws;
     r->dst2 = ws + r->m;
-    r->counts = ws + 2 * r->m;
-    r->sums = r->counts + (long long)r->K * r->G;
+    r->tmp_src = ws + 2 * r->m;
+    r->tmp_dst = ws + 3 * r->m;
+    r->counts = ws + 4 * r->m;
+    r->sums = r->counts + (long long)kDigits * r->G;
 }
 
 int enqueue_reorder(const Reorder& r, const int* src, const int* dst, hipStream_t stream)
 {
-    const long long cells = (long long)r.K * r.G;
-    hipLaunchKernelGGL(k_bucket_count, dim3(r.G), dim3(256), 0, stream, src, r.m, r.chunk, r.shift, r.K, r.counts);
-    hipLaunchKernelGGL(k_scan_local, dim3(r.nblk), dim3(kScanThreads), 0, stream, r.counts, cells, r.sums);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, stream, r.sums, r.nblk);
-    hipLaunchKernelGGL(k_scan_add, dim3(r.nblk), dim3(kScanThreads), 0, stream, r.counts, cells, (const int*)r.sums);
-    hipLaunchKernelGGL(k_bucket_scatter, dim3(r.G), dim3(256), 0, stream, src, dst, r.m, r.chunk, r.shift, r.K,
-                       (const int*)r.counts, r.src2, r.dst2);
+    const long long cells = (long long)kDigits * r.G;
+    // the last pass writes src2/dst2; earlier passes alternate through tmp
+    const int* in_s = src;
+    const int* in_d = dst;
+    for (int pass = 0; pass < r.passes; ++pass) {
+        int* out_s = ((r.passes - 1 - pass) & 1) ? r.tmp_src : r.src2;
+        int* out_d = ((r.passes - 1 - pass) & 1) ? r.tmp_dst : r.dst2;
+        hipLaunchKernelGGL(k_rx_count, dim3(r.G), dim3(kRxThreads), 0, stream, in_s, r.m, r.shift, r.K, pass, r.counts);
+        hipLaunchKernelGGL(k_scan_local, dim3(r.nblk), dim3(kScanThreads), 0, stream, r.counts, cells, r.sums);
+        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, stream, r.sums, r.nblk);
+        hipLaunchKernelGGL(k_scan_add, dim3(r.nblk), dim3(kScanThreads), 0, stream, r.counts, cells,
+                           (const int*)r.sums);
+        hipLaunchKernelGGL(k_rx_scatter, dim3(r.G), dim3(kRxThreads), 0, stream, in_s, in_d, r.m, r.shift, r.K, pass,
+                           (const int*)r.counts, out_s, out_d);
+        in_s = out_s;
+        in_d = out_d;
+    }
     CONTOUR_HIP(hipGetLastError());
     return CONTOUR_OK;
 }

@@ -73,16 +73,19 @@ void timing_events(hipEvent_t* begin, hipEvent_t* end);
 
 // Edge reordering by source block (contour_reorder.hip).
 struct Reorder {
-    int shift = 0;          // bucket = src >> shift
-    int K = 0;              // buckets
-    int G = 0;              // workgroups of the count and scatter passes
-    long long chunk = 0;    // edges per workgroup
+    int shift = 0;          // source block = src >> shift
+    int K = 0;              // source blocks
+    int passes = 0;         // radix passes of 5 bits
+    int G = 0;              // workgroups (chunks) of the count and scatter passes
+    long long chunk = 0;    // edges per chunk
     int nblk = 0;           // scan blocks
     long long m = 0;
     long long elems = 0;    // workspace ints needed
     int* src2 = nullptr;    // workspace: reordered edges
     int* dst2 = nullptr;
-    int* counts = nullptr;  // workspace: K x G matrix
+    int* tmp_src = nullptr; // workspace: intermediate pass
+    int* tmp_dst = nullptr;
+    int* counts = nullptr;  // workspace: 32 x G digit counts
     int* sums = nullptr;    // workspace: scan block totals
 };
 
@@ -102,6 +105,7 @@ struct PersistentLaunch {
     SolveArgs args;
     unsigned grid;
     int block;
+    size_t lds;                 // dynamic LDS bytes (label window)
     unsigned init_blocks;
     int warm;
     int n;

@@ -59,10 +59,10 @@ __global__ void k_write_stats(const Ctl* c, contour_stats_t* out, int range_err)
 // ------------------------------------------------- persistent driver ----
 // One launch for the whole solve; the sweep loop is persistent_solve() in
 // contour_persistent.hpp.
-template <int EPT, int BLOCK, bool ATOMIC>
+template <int EPT, int BLOCK, bool ATOMIC, bool WIN>
 __global__ __launch_bounds__(BLOCK) void k_persistent(SolveArgs a)
 {
-    persistent_solve<EPT, BLOCK, ATOMIC>(a);
+    persistent_solve<EPT, BLOCK, ATOMIC, WIN>(a);
 }
 
 // ------------------------------------------------- host-loop driver -----
@@ -119,34 +119,49 @@ __global__ void k_copy_labels(const int* R, int* W, unsigned n, const Ctl* c)
 typedef void (*persistent_fn)(SolveArgs);
 typedef void (*sweep_fn)(SolveArgs, const int*, int*, int);
 
-// 1024-thread workgroups get at most 128 registers per lane, which eight
-// edges per thread of the persistent loop exceed: they use four.
-template <int BLOCK, bool ATOMIC>
+// Register limits: 1024-thread workgroups get at most 128 registers per
+// lane and 512-thread ones 256.  Edges per thread of the persistent loop are
+// capped where the compiler would otherwise spill: eight become four (1024
+// threads, or 512 with a label window), and with a label window 1024-thread
+// workgroups take at most two.
+template <int BLOCK, bool WIN>
+struct EptCap {
+    static constexpr int e8 = (BLOCK == 1024 || (BLOCK == 512 && WIN)) ? 4 : 8;
+    static constexpr int e4 = (BLOCK == 1024 && WIN) ? 2 : 4;
+};
+
+template <int BLOCK, bool ATOMIC, bool WIN>
 static void pick(int ept, persistent_fn* p, sweep_fn* s)
 {
+    constexpr int e4 = EptCap<BLOCK, WIN>::e4;
+    constexpr int e8 = EptCap<BLOCK, WIN>::e8 < e4 ? e4 : EptCap<BLOCK, WIN>::e8 == 4 ? e4 : 8;
     switch (ept) {
-    case 1: *p = k_persistent<1, BLOCK, ATOMIC>; *s = k_sweep<1, BLOCK, ATOMIC>; break;
-    case 2: *p = k_persistent<2, BLOCK, ATOMIC>; *s = k_sweep<2, BLOCK, ATOMIC>; break;
-    case 4: *p = k_persistent<4, BLOCK, ATOMIC>; *s = k_sweep<4, BLOCK, ATOMIC>; break;
-    default:
-        *p = BLOCK == 1024 ? k_persistent<4, BLOCK, ATOMIC> : k_persistent<8, BLOCK, ATOMIC>;
-        *s = k_sweep<8, BLOCK, ATOMIC>;
-        break;
+    case 1: *p = k_persistent<1, BLOCK, ATOMIC, WIN>; *s = k_sweep<1, BLOCK, ATOMIC>; break;
+    case 2: *p = k_persistent<2, BLOCK, ATOMIC, WIN>; *s = k_sweep<2, BLOCK, ATOMIC>; break;
+    case 4: *p = k_persistent<e4, BLOCK, ATOMIC, WIN>; *s = k_sweep<4, BLOCK, ATOMIC>; break;
+    default: *p = k_persistent<e8, BLOCK, ATOMIC, WIN>; *s = k_sweep<(BLOCK == 1024 ? 4 : 8), BLOCK, ATOMIC>; break;
     }
 }
 
-static void pick_kernels(int block, int ept, bool atomic, persistent_fn* p, sweep_fn* s)
+template <bool WIN>
+static void pick_w(int block, int ept, bool atomic, persistent_fn* p, sweep_fn* s)
 {
     if (block == 1024) {
-        if (atomic) pick<1024, true>(ept, p, s);
-        else pick<1024, false>(ept, p, s);
+        if (atomic) pick<1024, true, WIN>(ept, p, s);
+        else pick<1024, false, WIN>(ept, p, s);
     } else if (block == 512) {
-        if (atomic) pick<512, true>(ept, p, s);
-        else pick<512, false>(ept, p, s);
+        if (atomic) pick<512, true, WIN>(ept, p, s);
+        else pick<512, false, WIN>(ept, p, s);
     } else {
-        if (atomic) pick<256, true>(ept, p, s);
-        else pick<256, false>(ept, p, s);
+        if (atomic) pick<256, true, WIN>(ept, p, s);
+        else pick<256, false, WIN>(ept, p, s);
     }
+}
+
+static void pick_kernels(int block, int ept, bool atomic, persistent_fn* p, sweep_fn* s, bool win = false)
+{
+    if (win) pick_w<true>(block, ept, atomic, p, s);
+    else pick_w<false>(block, ept, atomic, p, s);
 }
 
 static bool wants_reorder(const Resolved& r, long long m, int n)
@@ -185,11 +200,13 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
                        long long m, int n, int* L, Ctl* ctl, int* ws, PersistentLaunch* out)
 {
     Resolved r = r0;
+    const bool reorder = m > 0 && wants_reorder(r0, m, n);
+    if (reorder && r.ept == 0) r.ept = 2;  // label-window tasks: most gathers hit LDS
     auto_geometry(d, m, &r);
     PersistentLaunch p;
     p.src_in = src;
     p.dst_in = dst;
-    p.reorder = m > 0 && wants_reorder(r, m, n);
+    p.reorder = reorder;
     if (p.reorder) {
         if (!ws) return CONTOUR_EINVAL;
         reorder_geometry(d, m, n, &p.ro);
@@ -214,17 +231,38 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
     a.watchdog = watchdog_ticks(d);
     a.tiles_per_task = 1;
     a.tasks = 0;
+    a.win_cap = 0;
+    a.win_shift = 0;
+    a.win_margin = 0;
     p.kernel = nullptr;
     p.grid = 0;
+    p.lds = 0;
     if (m > 0) {
         sweep_fn ks;
-        pick_kernels(r.block, r.ept, r.atomic, &p.kernel, &ks);
+        const bool win = p.reorder;
+        pick_kernels(r.block, r.ept, r.atomic, &p.kernel, &ks, win);
+        if (win) {
+            // the largest window (labels + one dirty bit each) that fits the
+            // LDS of one workgroup, a multiple of 32 labels
+            const long long bytes = std::max(0, d.max_lds_per_block - 2048);
+            a.win_cap = (int)std::min<long long>(((bytes * 32) / 132) & ~31LL, (long long)n + 31);
+            a.win_shift = p.ro.shift;
+            a.win_margin = std::max(1, (1 << p.ro.shift) / 2);
+            p.lds = (size_t)a.win_cap * 4 + (size_t)((a.win_cap + 31) / 32) * 4;
+            CONTOUR_HIP(hipFuncSetAttribute((const void*)p.kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)p.lds));
+        }
         const long long tile_edges = (long long)r.block * r.ept;
         const long long ntiles = (m + tile_edges - 1) / tile_edges;
         int occ = 0;
-        CONTOUR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)p.kernel, r.block, 0));
+        CONTOUR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)p.kernel, r.block, p.lds));
         const long long resident = (long long)std::max(occ, 1) * d.cus;
-        const int tpt = r.chunk_tiles ? r.chunk_tiles : auto_tiles_per_task(m, tile_edges);
+        int tpt = r.chunk_tiles ? r.chunk_tiles : auto_tiles_per_task(m, tile_edges);
+        if (win && !r.chunk_tiles) {
+            // a window is loaded per task: tasks of m / 1024 edges, 32 Ki to 256 Ki
+            const long long want = std::max<long long>(32768, std::min<long long>(262144, m / 1024));
+            tpt = (int)std::max<long long>(1, want / tile_edges);
+        }
         a.tiles_per_task = tpt;
         a.tasks = (ntiles + tpt - 1) / tpt;
         p.grid = (unsigned)(r.grid ? r.grid : std::min<long long>(resident, a.tasks));
@@ -247,7 +285,7 @@ int enqueue_persistent(const PersistentLaunch& p, contour_stats_t* stats, hipStr
     CONTOUR_HIP(hipGetLastError());
     if (ev_begin) CONTOUR_HIP(hipEventRecord(ev_begin, stream));
     if (p.kernel) {
-        hipLaunchKernelGGL(p.kernel, dim3(p.grid), dim3(p.block), 0, stream, p.args);
+        hipLaunchKernelGGL(p.kernel, dim3(p.grid), dim3(p.block), p.lds, stream, p.args);
         CONTOUR_HIP(hipGetLastError());
     }
     if (ev_end) CONTOUR_HIP(hipEventRecord(ev_end, stream));
@@ -307,6 +345,9 @@ static int run_hostloop(const DeviceInfo& d, const Resolved& r0, const int* src,
         a.max_sweeps = r.max_sweeps;
         a.ctl = ws->ctl;
         a.watchdog = watchdog_ticks(d);
+        a.win_cap = 0;
+        a.win_shift = 0;
+        a.win_margin = 0;
         const long long tile_edges = (long long)r.block * r.ept;
         const long long ntiles = (m + tile_edges - 1) / tile_edges;
         a.tiles_per_task = 1;

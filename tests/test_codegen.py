@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2311_02811_amd", "csrc")
 
 
-@pytest.mark.parametrize("src", ["contour_single.hip", "contour_batch.hip"])
+@pytest.mark.parametrize("src", ["contour_single.hip", "contour_batch.hip", "contour_reorder.hip"])
 def test_no_divergent_loop_around_a_barrier(src, tmp_path):
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(hipcc):
@@ -30,6 +30,15 @@ def test_no_divergent_loop_around_a_barrier(src, tmp_path):
     subprocess.run(cmd, check=True, capture_output=True)
     bad = check_file(str(out))
     assert not bad, bad
+    # no kernel may spill vector registers to scratch memory
+    import re
+    spills = []
+    for blk in out.read_text().split("  - ."):
+        name = re.search(r"\.name:\s+(\S+)", blk)
+        spill = re.search(r"\.vgpr_spill_count:\s+(\d+)", blk)
+        if name and spill and int(spill.group(1)) > 0:
+            spills.append((name.group(1), int(spill.group(1))))
+    assert not spills, spills
 
 
 def test_checker_flags_a_divergent_barrier_loop(tmp_path):
