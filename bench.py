@@ -101,6 +101,162 @@ def time_gpu(contour, torch, src, dst, n, steps, warmup, opts):
                 labels=labels.cpu().numpy())
 
 
+def pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
+
+
+def bench_plain_extra(contour, torch, name, seed, steps, orders):
+    """Throughput of the plain single-graph solve on another workload."""
+    src, dst, n = make_workload(name, seed)
+    out = {"n": n, "m": int(src.size)}
+    for order in orders:
+        r = time_gpu(contour, torch, src, dst, n, steps, 1, dict(order=order))
+        ms = r["total_ms"] / steps
+        sw = [x[1] for x in r["stats"]]
+        km = statistics.mean(r["kernel_ms"])
+        key = "order_%s" % order
+        out[key] = {"ms_per_solve": round(ms, 4), "edges_per_s": round(src.size / ms * 1e3, 1),
+                    "sweeps_mean": statistics.mean(sw), "sweep_kernel_ms": round(km, 4)}
+        bpe = bytes_per_edge_sweep(order)
+        if bpe:
+            out[key]["alg_GBps"] = round(statistics.mean(sw) * src.size * bpe / (km / 1e3) / 1e9, 1)
+    return out
+
+
+def bench_batched(contour, torch, seed, steps):
+    """20,000 graphs in one plan launch vs one plain launch per graph."""
+    import numpy as np
+    import graphgen
+    b = graphgen.batch(20000, seed)
+    s = torch.from_numpy(b.src).cuda()
+    d = torch.from_numpy(b.dst).cuda()
+    plan = contour.BatchPlan(b.edge_off, b.vertex_off, s, d)
+    stream = torch.cuda.current_stream()
+    plan.launch()
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        plan.launch()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    batched_labels = plan.labels.cpu().numpy()
+    classes = plan.classes()
+    sweeps = plan.stats[:, 1].float().mean().item()
+    plan.close()
+    # baseline: one contour_cc per graph, same device-resident data, same stream
+    labels = torch.empty(int(b.vertex_off[-1]), dtype=torch.int32, device="cuda")
+    lib = contour.load()
+    eo, vo = b.edge_off, b.vertex_off
+    sp, dp, lp = s.data_ptr(), d.data_ptr(), labels.data_ptr()
+    h = ctypes.c_void_p(stream.cuda_stream)
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    for g in range(b.num_graphs):
+        lib.contour_cc(ctypes.c_void_p(sp + 4 * int(eo[g])), ctypes.c_void_p(dp + 4 * int(eo[g])),
+                       int(eo[g + 1] - eo[g]), int(vo[g + 1] - vo[g]),
+                       ctypes.c_void_p(lp + 4 * int(vo[g])), h)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_base = max(t0.elapsed_time(t1), wall * 1e3)
+    same = bool(np.array_equal(labels.cpu().numpy(), batched_labels))
+    G, M = b.num_graphs, int(b.m.sum())
+    return {"graphs": G, "sum_n": int(b.n.sum()), "sum_m": M, "classes": classes,
+            "ms_per_batch": round(ms, 3), "graphs_per_s": round(G / ms * 1e3, 1),
+            "edges_per_s": round(M / ms * 1e3, 1), "sweeps_mean": round(sweeps, 3),
+            "per_graph_plain_ms": round(ms_base, 3),
+            "per_graph_plain_graphs_per_s": round(G / ms_base * 1e3, 1),
+            "speedup_vs_per_graph": round(ms_base / ms, 2), "identical_labels": same}, b
+
+
+def bench_serving(contour, torch, seed, batch, seconds, rate):
+    """Poisson arrivals: micro-batched serving loop vs FIFO plain launches."""
+    import numpy as np
+    import graphgen
+    big_pool = []
+    for k in range(2):
+        s2, d2 = graphgen.rmat(22, 16, seed + 100 + k)
+        big_pool.append((torch.from_numpy(s2).pin_memory(), torch.from_numpy(d2).pin_memory(), 1 << 22))
+    src_p = torch.from_numpy(batch.src).pin_memory()
+    dst_p = torch.from_numpy(batch.dst).pin_memory()
+    count = int(seconds * rate)
+    t_arr, big, pick = graphgen.poisson_trace(count, rate, 0.01, batch.num_graphs, len(big_pool), seed)
+
+    def req(i):
+        if big[i]:
+            return big_pool[int(pick[i])]
+        g = int(pick[i])
+        a, b_ = int(batch.edge_off[g]), int(batch.edge_off[g + 1])
+        return src_p[a:b_], dst_p[a:b_], int(batch.n[g])
+
+    outs = [torch.empty(max(req(i)[2], 1), dtype=torch.int32).pin_memory() for i in range(count)]
+    # served
+    srv = contour.Server(lanes=4)
+    t_start = time.perf_counter() + 0.05
+    ids = []
+    for i in range(count):
+        while time.perf_counter() < t_start + t_arr[i]:
+            pass
+        s_, d_, n_ = req(i)
+        ids.append(srv.submit(s_, d_, n_, outs[i]))
+    srv.drain()
+    res = {}
+    while True:
+        got = srv.poll(8192)
+        if not got:
+            break
+        for r in got:
+            res[r["id"]] = r
+    srv.close()
+    lat = [(res[i]["t_done_ns"] - res[i]["t_submit_ns"]) / 1e6 for i in ids]
+    t_first = min(res[i]["t_submit_ns"] for i in ids)
+    t_last = max(res[i]["t_done_ns"] for i in ids)
+    span = (t_last - t_first) / 1e9
+    edges = sum(len(req(i)[0]) for i in range(count))
+    ok = all(res[i]["status"] == 0 for i in ids)
+    # FIFO baseline: one plain solve per request in arrival order
+    lib = contour.load()
+    stream = torch.cuda.current_stream()
+    h = ctypes.c_void_p(stream.cuda_stream)
+    maxm = max(len(req(i)[0]) for i in range(count))
+    maxn = max(req(i)[2] for i in range(count))
+    ds = torch.empty(maxm, dtype=torch.int32, device="cuda")
+    dd = torch.empty(maxm, dtype=torch.int32, device="cuda")
+    dl = torch.empty(maxn, dtype=torch.int32, device="cuda")
+    base_out = [torch.empty_like(o) for o in outs]
+    lat_b = []
+    same = True
+    t0 = time.perf_counter() + 0.05
+    for i in range(count):
+        arrive = t0 + t_arr[i]
+        while time.perf_counter() < arrive:
+            pass
+        s_, d_, n_ = req(i)
+        m_ = len(s_)
+        if m_:
+            ds[:m_].copy_(s_, non_blocking=True)
+            dd[:m_].copy_(d_, non_blocking=True)
+        lib.contour_cc(ctypes.c_void_p(ds.data_ptr()), ctypes.c_void_p(dd.data_ptr()), m_, n_,
+                       ctypes.c_void_p(dl.data_ptr()), h)
+        base_out[i][:n_].copy_(dl[:n_], non_blocking=True)
+        stream.synchronize()
+        lat_b.append((time.perf_counter() - arrive) * 1e3)
+    span_b = time.perf_counter() - t0 - t_arr[0]
+    for i in range(0, count, max(1, count // 200)):
+        n_ = req(i)[2]
+        same &= bool(torch.equal(outs[i][:n_], base_out[i][:n_]))
+    return {"requests": count, "rate_per_s": rate, "seconds": seconds, "big_requests": int(big.sum()),
+            "all_ok": ok, "identical_to_plain": same,
+            "served": {"p50_ms": round(pct(lat, 50), 3), "p99_ms": round(pct(lat, 99), 3),
+                       "graphs_per_s": round(count / span, 1), "edges_per_s": round(edges / span, 1)},
+            "fifo_plain": {"p50_ms": round(pct(lat_b, 50), 3), "p99_ms": round(pct(lat_b, 99), 3),
+                           "graphs_per_s": round(count / span_b, 1),
+                           "edges_per_s": round(edges / span_b, 1)}}
+
+
 def cpu_baseline(src, dst, n, budget_s):
     import oracle
     times = []
@@ -133,6 +289,9 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--edges-per-thread", type=int, default=0)
     ap.add_argument("--chunk-tiles", type=int, default=0)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the R-MAT, ER, batched and serving measurements")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized int32 buffer --steps times (HBM counter calibration)")
     args = ap.parse_args()
@@ -213,6 +372,20 @@ def main():
                                "sample": "sequential union-find on the whole workload graph, "
                                          "%d runs, median %.3f s" % (len(times), t)}
         out["exact"] = bool(np.array_equal(lab, r["labels"]))
+    if not args.no_extras:
+        extras = {}
+        log("extra: R-MAT scale 24")
+        extras["rmat24_ef16"] = bench_plain_extra(contour, torch, "rmat24_ef16", args.seed, 3,
+                                                  [2, 3, "full"])
+        log("extra: ER n=65536 m=524288")
+        extras["er65536_m524288"] = bench_plain_extra(contour, torch, "er65536_m524288", args.seed,
+                                                      20, [2, 1])
+        log("extra: batched 20,000 graphs")
+        extras["batched20000"], batch = bench_batched(contour, torch, args.seed, 3)
+        log("extra: serving, Poisson 2000/s for %.1f s" % args.serve_seconds)
+        extras["serving_poisson2000"] = bench_serving(contour, torch, args.seed, batch,
+                                                      args.serve_seconds, 2000.0)
+        out["extras"] = extras
     print(json.dumps(out), flush=True)
 
 

@@ -15,7 +15,8 @@ from __future__ import annotations
 import ctypes
 from dataclasses import dataclass
 
-from ._lib import BatchTuning, ContourBatch, ContourOpts, load, lib_path  # noqa: F401
+from ._lib import (BatchTuning, ContourBatch, ContourOpts, RequestResult, ServerConfig,  # noqa: F401
+                   load, lib_path)
 
 ORDER_FULL = -1
 _SCHED = {"fixed": 0, "11mm": 1, "1m1m": 2}
@@ -231,3 +232,81 @@ def cc_batched(edge_off, vertex_off, src, dst, labels=None, stream=None, **opts)
         return plan.labels, plan.stats
     finally:
         plan.close()
+
+
+class Server:
+    """Serving loop of contour_serve.h: submit host graphs as they arrive,
+    poll finished requests.  Host arrays should be pinned (torch tensors with
+    pin_memory=True, or any buffer from hipHostMalloc); the caller keeps each
+    request's arrays alive until it is reported done."""
+
+    def __init__(self, hbm_budget_bytes=0, lanes=0, batch_max=0, small_edges=0, **opts):
+        lib = load()
+        c = ServerConfig()
+        lib.contour_server_default_config(ctypes.byref(c))
+        c.hbm_budget_bytes = int(hbm_budget_bytes)
+        c.lanes = int(lanes)
+        c.batch_max = int(batch_max)
+        c.small_edges = int(small_edges)
+        c.opts = make_opts(**opts)
+        h = ctypes.c_void_p()
+        rc = lib.contour_server_create(ctypes.byref(c), ctypes.byref(h))
+        if rc != OK:
+            raise ContourError(rc, "contour_server_create")
+        self._h = h
+        self._keep = {}
+
+    @staticmethod
+    def now_ns() -> int:
+        return int(load().contour_server_now_ns())
+
+    def submit(self, src, dst, n: int, labels) -> int:
+        """src, dst: host int32 tensors (or numpy arrays) of m ids; labels:
+        host int32 buffer of n entries, written when the request is done."""
+        def ptr(a):
+            if a is None:
+                return None
+            if hasattr(a, "data_ptr"):
+                return a.data_ptr()
+            return a.ctypes.data
+        rid = ctypes.c_int64()
+        m = len(src)
+        rc = load().contour_server_submit(self._h, ptr(src) if m else None,
+                                          ptr(dst) if m else None, m, int(n),
+                                          ptr(labels) if n else None, ctypes.byref(rid))
+        if rc != OK:
+            raise ContourError(rc, "contour_server_submit")
+        self._keep[rid.value] = (src, dst, labels)
+        return rid.value
+
+    def poll(self, max_results=1024, wait_us=0):
+        buf = (RequestResult * max(int(max_results), 1))()
+        cnt = ctypes.c_int32()
+        rc = load().contour_server_poll(self._h, buf, int(max_results), int(wait_us),
+                                        ctypes.byref(cnt))
+        if rc != OK:
+            raise ContourError(rc, "contour_server_poll")
+        out = []
+        for i in range(cnt.value):
+            r = buf[i]
+            self._keep.pop(r.id, None)
+            out.append(dict(id=r.id, status=r.status, sweeps=r.sweeps_executed,
+                            t_submit_ns=r.t_submit_ns, t_admit_ns=r.t_admit_ns,
+                            t_done_ns=r.t_done_ns))
+        return out
+
+    def drain(self):
+        rc = load().contour_server_drain(self._h)
+        if rc != OK:
+            raise ContourError(rc, "contour_server_drain")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().contour_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

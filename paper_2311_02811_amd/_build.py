@@ -22,6 +22,7 @@ SOURCES = [
     "contour_single.hip",
     "contour_batch.hip",
     "contour_reorder.hip",
+    "contour_serve.cpp",
 ]
 
 HIPCC_FLAGS = [

@@ -48,6 +48,18 @@ class BatchTuning(ctypes.Structure):
                 ("wg_max_edges", ctypes.c_int32)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("lanes", ctypes.c_int32),
+                ("batch_max", ctypes.c_int32), ("small_edges", ctypes.c_int64),
+                ("opts", ContourOpts)]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32),
+                ("sweeps_executed", ctypes.c_int32), ("t_submit_ns", ctypes.c_int64),
+                ("t_admit_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64)]
+
+
 # Exported symbols and their C signatures (restype, argtypes).
 SIGNATURES = {
     "contour_default_opts": (None, [ctypes.POINTER(ContourOpts)]),
@@ -73,6 +85,18 @@ SIGNATURES = {
     "contour_batch_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "contour_cc_batched": (ctypes.c_int, [ctypes.POINTER(ContourBatch), ctypes.POINTER(ContourOpts),
                                           ctypes.c_void_p]),
+    "contour_server_default_config": (None, [ctypes.POINTER(ServerConfig)]),
+    "contour_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig),
+                                             ctypes.POINTER(ctypes.c_void_p)]),
+    "contour_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                             ctypes.POINTER(ctypes.c_int64)]),
+    "contour_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RequestResult),
+                                           ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_int32)]),
+    "contour_server_drain": (ctypes.c_int, [ctypes.c_void_p]),
+    "contour_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "contour_server_now_ns": (ctypes.c_int64, []),
 }
 
 OPTIONAL_SIGNATURES = {}

@@ -29,18 +29,7 @@
 
 namespace contour {
 
-struct BatchJob {
-    long long e0;  // first edge of the graph
-    long long m;   // edge count
-    long long v0;  // first label of the graph
-    int n;         // vertex count
-    int g;         // graph index in the batch (for stats)
-};
-
 struct WgArgs {
-    const int* src;
-    const int* dst;
-    int* labels;
     contour_stats_t* stats;  // [G] or null
     const BatchJob* jobs;
     int njobs;
@@ -61,8 +50,8 @@ __device__ __forceinline__ void wg_solve(const WgArgs& a, const BatchJob& job, i
     __syncthreads();
     const long long tile_edges = (long long)BLOCK * EPT;
     const long long ntiles = (job.m + tile_edges - 1) / tile_edges;
-    const int* src = a.src + job.e0;
-    const int* dst = a.dst + job.e0;
+    const int* src = job.src;
+    const int* dst = job.dst;
     int sweep = 0, last_change = 0, rerr = 0, state = ST_CONVERGED;
     if (job.m > 0) {
         for (;;) {
@@ -89,7 +78,7 @@ __device__ __forceinline__ void wg_solve(const WgArgs& a, const BatchJob& job, i
     }
     const int anyerr = uniform(__syncthreads_or(rerr));
     if (lds)
-        for (int i = threadIdx.x; i < job.n; i += BLOCK) a.labels[job.v0 + i] = L[i];
+        for (int i = threadIdx.x; i < job.n; i += BLOCK) job.labels[i] = L[i];
     if (a.stats && threadIdx.x == 0) {
         contour_stats_t st;
         st.status = anyerr ? CONTOUR_ERANGE : (state == ST_CONVERGED ? CONTOUR_OK : CONTOUR_ENOCONV);
@@ -114,7 +103,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_wg(WgArgs a)
         if (LDS)
             wg_solve<EPT, BLOCK, ATOMIC>(a, job, lds_labels, true);
         else
-            wg_solve<EPT, BLOCK, ATOMIC>(a, job, a.labels + job.v0, false);
+            wg_solve<EPT, BLOCK, ATOMIC>(a, job, job.labels, false);
         __syncthreads();  // every lane has read s_job and finished with LDS
         if (threadIdx.x == 0) s_job = atomicAdd(a.counter, 1);
         __syncthreads();
@@ -262,6 +251,44 @@ static multi_fn pick_multi(int block, int ept, bool atomic)
     return atomic ? pick_multi_e<256, true>(ept) : pick_multi_e<256, false>(ept);
 }
 
+static int wg_occupancy(wg_fn k, int block, size_t lds, int* occ)
+{
+    *occ = 0;
+    CONTOUR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, (const void*)k, block, lds));
+    return CONTOUR_OK;
+}
+
+int enqueue_wg_jobs(const DeviceInfo& d, const Resolved& r, const BatchJob* d_jobs, int n_lds, int max_n_lds,
+                    int n_global, int* d_counters, Ctl* d_clock, contour_stats_t* stats, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, stream, d_counters, d_clock);
+    const int counts[2] = {n_lds, n_global};
+    for (int c = 1; c >= 0; --c) {
+        if (counts[c] == 0) continue;
+        const int block = r.block ? std::min(r.block, 1024) : 512;
+        const int ept = r.ept ? std::min(r.ept, 4) : (c == 0 ? 1 : 2);
+        WgArgs a;
+        a.stats = stats;
+        a.jobs = d_jobs + (c == 0 ? 0 : n_lds);
+        a.njobs = counts[c];
+        a.counter = d_counters + c;
+        a.sched = r.sched;
+        a.max_sweeps = r.max_sweeps;
+        a.clock = d_clock;
+        a.watchdog = watchdog_ticks(d);
+        const wg_fn k = pick_wg(block, ept, r.atomic, c == 0);
+        const size_t lds = c == 0 ? sizeof(int) * (size_t)std::max(max_n_lds, 1) : 0;
+        if (c == 0) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        int occ = 0;
+        int rc = wg_occupancy(k, block, lds, &occ);
+        if (rc) return rc;
+        const unsigned grid = (unsigned)std::min<long long>((long long)std::max(occ, 1) * d.cus, counts[c]);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds, stream, a);
+        CONTOUR_HIP(hipGetLastError());
+    }
+    return CONTOUR_OK;
+}
+
 }  // namespace contour
 
 // ----------------------------------------------------------------- plan --
@@ -392,9 +419,10 @@ static int create_plan(const contour_batch_t* b, const contour_opts_t* opts, con
     std::vector<int> big;
     for (int g : idx) {
         BatchJob j;
-        j.e0 = eo[g];
+        j.src = b->src + eo[g];
+        j.dst = b->dst + eo[g];
+        j.labels = b->labels_out + vo[g];
         j.m = eo[g + 1] - eo[g];
-        j.v0 = vo[g];
         j.n = (int)(vo[g + 1] - vo[g]);
         j.g = g;
         if (j.n <= lds_max)
@@ -420,9 +448,6 @@ static int create_plan(const contour_batch_t* b, const contour_opts_t* opts, con
     const unsigned long long wd = watchdog_ticks(d);
     for (int c = 0; c < 2; ++c) {
         WgArgs& a = p->wg[c];
-        a.src = b->src;
-        a.dst = b->dst;
-        a.labels = b->labels_out;
         a.stats = b->stats_out;
         a.jobs = p->d_jobs + (c == 0 ? 0 : jobs[0].size());
         a.njobs = (int)jobs[c].size();

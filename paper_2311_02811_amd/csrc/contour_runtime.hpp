@@ -71,6 +71,26 @@ unsigned long long watchdog_ticks(const DeviceInfo& d);
 // Per-thread timing events set by contour_set_timing_events (may be null).
 void timing_events(hipEvent_t* begin, hipEvent_t* end);
 
+// One graph of a batch solved by a single workgroup (contour_batch.hip):
+// its own edge and label arrays, local ids.
+struct BatchJob {
+    const int* src;
+    const int* dst;
+    int* labels;
+    long long m;  // edge count
+    int n;        // vertex count
+    int g;        // index for stats
+};
+
+// Enqueue single-workgroup solves of `count` jobs whose table is already in
+// device memory (d_jobs), on `stream`, without allocating: graphs with
+// n <= lds_max keep their labels in LDS (one launch sized for the largest
+// such n), the rest in global memory.  d_counters: 4 ints; d_clock: one Ctl.
+// Jobs must be ordered so that the LDS ones (n <= lds_max) come first;
+// n_lds of them, max_n_lds their largest n.
+int enqueue_wg_jobs(const DeviceInfo& d, const Resolved& r, const BatchJob* d_jobs, int n_lds, int max_n_lds,
+                    int n_global, int* d_counters, Ctl* d_clock, contour_stats_t* stats, hipStream_t stream);
+
 // Edge reordering by source block (contour_reorder.hip).
 struct Reorder {
     int shift = 0;          // source block = src >> shift
