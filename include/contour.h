@@ -105,8 +105,10 @@ typedef struct {
     int32_t chunk_tiles; /* persistent driver: tiles (block * edges_per_thread edges)
                             per task, 0 = auto */
     int32_t grid;        /* workgroups, 0 = auto (all resident) */
-    int32_t reorder;     /* CONTOUR_REORDER_*: bucket the edges by source-vertex block
-                            before the sweeps (a counting sort on device) */
+    int32_t reorder;     /* CONTOUR_REORDER_*: group the edges by source-vertex block
+                            before the sweeps (a radix partition on device) */
+    int32_t window;      /* with reordering: labels staged in LDS per task, 0 = as many
+                            as one workgroup's LDS holds; at least 1024 */
 } contour_opts_t;
 
 /* Edge reordering.  The sweeps may apply MM^h to the edges in any order

@@ -72,7 +72,7 @@ def _check_edges(src, dst):
 
 def make_opts(order=2, schedule="fixed", k1=2, write="plain", update="async",
               driver="persistent", max_sweeps=0, warm_start=False, block=0,
-              edges_per_thread=0, chunk_tiles=0, grid=0, reorder="auto") -> ContourOpts:
+              edges_per_thread=0, chunk_tiles=0, grid=0, reorder="auto", window=0) -> ContourOpts:
     o = ContourOpts()
     load().contour_default_opts(ctypes.byref(o))
     o.order = ORDER_FULL if order in ("full", ORDER_FULL) else int(order)
@@ -88,6 +88,7 @@ def make_opts(order=2, schedule="fixed", k1=2, write="plain", update="async",
     o.chunk_tiles = int(chunk_tiles)
     o.grid = int(grid)
     o.reorder = _REORDER[reorder]
+    o.window = int(window)
     return o
 
 

@@ -20,7 +20,7 @@ c_i64p = ctypes.POINTER(ctypes.c_int64)
 class ContourOpts(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in (
         "order", "schedule", "k1", "write_mode", "update", "driver", "max_sweeps", "warm_start",
-        "block", "edges_per_thread", "chunk_tiles", "grid", "reorder")]
+        "block", "edges_per_thread", "chunk_tiles", "grid", "reorder", "window")]
 
 
 class ContourStats(ctypes.Structure):

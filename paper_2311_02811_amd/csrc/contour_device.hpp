@@ -294,58 +294,71 @@ __device__ __forceinline__ bool tile_orderh(const LAB& lab, const int (&w)[EPT],
 }
 
 // Apply MM^ORDER (ORDER 0: the run-time order h) to the tiles
-// [first, first + count) of the edge list, stopping at m.
-template <int ORDER, int EPT, int BLOCK, bool ATOMIC, class LAB>
+// first, first + stride, ... (count of them), stopping at m.  The edges of
+// the next DEPTH-1 tiles are in flight while a tile is processed (a ring of
+// register slots, unrolled so that every slot index is a constant), so the
+// edge stream's latency overlaps the label gathers.
+template <int ORDER, int EPT, int BLOCK, bool ATOMIC, class LAB, int DEPTH = 4>
 __device__ __forceinline__ bool run_tiles(const int* __restrict__ src, const int* __restrict__ dst,
                                           const LAB& lab, long long first, long long count,
                                           long long stride, long long m, unsigned n, int h, int& rerr)
 {
-    // The edges of tile i+1 are fetched before tile i is processed, so the
-    // edge stream's latency overlaps the label gathers of the current tile.
     const long long tile_edges = (long long)BLOCK * EPT;
-    bool pred = false;
+    const long long step = stride * tile_edges;
     long long base = first * tile_edges;
     if (count <= 0 || base >= m) return false;
-    int w[EPT], v[EPT], nw[EPT], nv[EPT];
-    bool ok[EPT], nok[EPT];
-    fetch_tile<EPT, BLOCK>(src, dst, base, m, w, v, ok);
-    for (long long i = 0; i < count; ++i) {
-        const long long next = base + stride * tile_edges;
-        const bool more = i + 1 < count && next < m;
-        if (more) fetch_tile<EPT, BLOCK>(src, dst, next, m, nw, nv, nok);
-        check_tile<EPT>(n, w, v, ok, rerr);
-        if (ORDER == 1) pred |= tile_order1<EPT, ATOMIC>(lab, w, v, ok);
-        else if (ORDER == 2) pred |= tile_order2<EPT, ATOMIC>(lab, w, v, ok);
-        else if (ORDER == 3) pred |= tile_order3<EPT, ATOMIC>(lab, w, v, ok);
-        else pred |= tile_orderh<EPT, ATOMIC>(lab, w, v, ok, h);
-        if (!more) break;
+    bool pred = false;
+    int w[DEPTH][EPT], v[DEPTH][EPT];
+    bool ok[DEPTH][EPT];
 #pragma unroll
-        for (int k = 0; k < EPT; ++k) {
-            w[k] = nw[k];
-            v[k] = nv[k];
-            ok[k] = nok[k];
+    for (int d = 0; d < DEPTH - 1; ++d) fetch_tile<EPT, BLOCK>(src, dst, base + d * step, m, w[d], v[d], ok[d]);
+    bool done = false;
+    for (long long i = 0; i < count && !done; i += DEPTH) {
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d) {
+            const long long tb = base + (long long)d * step;
+            if (i + d >= count || tb >= m) {
+                done = true;
+                break;
+            }
+            // refill the slot freed one round ago with tile i + d + DEPTH - 1
+            constexpr int ahead = DEPTH - 1;
+            const int slot = (d + ahead) % DEPTH;
+            fetch_tile<EPT, BLOCK>(src, dst, tb + ahead * step, m, w[slot], v[slot], ok[slot]);
+            check_tile<EPT>(n, w[d], v[d], ok[d], rerr);
+            if (ORDER == 1) pred |= tile_order1<EPT, ATOMIC>(lab, w[d], v[d], ok[d]);
+            else if (ORDER == 2) pred |= tile_order2<EPT, ATOMIC>(lab, w[d], v[d], ok[d]);
+            else if (ORDER == 3) pred |= tile_order3<EPT, ATOMIC>(lab, w[d], v[d], ok[d]);
+            else pred |= tile_orderh<EPT, ATOMIC>(lab, w[d], v[d], ok[d], h);
         }
-        base = next;
+        base += (long long)DEPTH * step;
     }
     return pred;
 }
 
-// Tiles first, first + stride, ... (count of them) under the order h.
-template <int EPT, int BLOCK, bool ATOMIC, class LAB>
+// Prefetch depth: tiles of edges in flight per thread, chosen so that the
+// registers fit the workgroup size (128 per lane at 1024 threads, 256 at 512)
+// without spilling.
+template <int EPT, int BLOCK>
+struct TileDepth {
+    static constexpr int value = BLOCK == 1024 ? (EPT == 1 ? 4 : EPT == 2 ? 2 : 1) : (EPT <= 2 ? 4 : 2);
+};
+
+template <int EPT, int BLOCK, bool ATOMIC, class LAB, int DEPTH = TileDepth<EPT, BLOCK>::value>
 __device__ __forceinline__ bool run_tiles_lab(const int* __restrict__ src, const int* __restrict__ dst,
                                               const LAB& lab, long long first, long long count,
                                               long long stride, long long m, unsigned n, int h, int& rerr)
 {
     switch (h) {
-    case 1: return run_tiles<1, EPT, BLOCK, ATOMIC>(src, dst, lab, first, count, stride, m, n, h, rerr);
-    case 2: return run_tiles<2, EPT, BLOCK, ATOMIC>(src, dst, lab, first, count, stride, m, n, h, rerr);
-    case 3: return run_tiles<3, EPT, BLOCK, ATOMIC>(src, dst, lab, first, count, stride, m, n, h, rerr);
+    case 1: return run_tiles<1, EPT, BLOCK, ATOMIC, LAB, DEPTH>(src, dst, lab, first, count, stride, m, n, h, rerr);
+    case 2: return run_tiles<2, EPT, BLOCK, ATOMIC, LAB, DEPTH>(src, dst, lab, first, count, stride, m, n, h, rerr);
+    case 3: return run_tiles<3, EPT, BLOCK, ATOMIC, LAB, DEPTH>(src, dst, lab, first, count, stride, m, n, h, rerr);
     default:
         // A chain strictly decreases until its root, so it has at most n
         // vertices: chase-to-root is the order n operator, and the bound also
         // caps every walk.
         if (h < 0 || (unsigned)h > n) h = (int)n;
-        return run_tiles<0, EPT, BLOCK, ATOMIC>(src, dst, lab, first, count, stride, m, n, h, rerr);
+        return run_tiles<0, EPT, BLOCK, ATOMIC, LAB, DEPTH>(src, dst, lab, first, count, stride, m, n, h, rerr);
     }
 }
 

@@ -139,8 +139,8 @@ __device__ __forceinline__ bool window_task(const SolveArgs& a, long long first_
     for (unsigned i = threadIdx.x; i < (cnt + 31) / 32; i += BLOCK) dirty[i] = 0;
     __syncthreads();
     const WindowLabels lab{wl, dirty, lo, cnt, a.L};
-    const bool pred = run_tiles_lab<EPT, BLOCK, ATOMIC>(a.src, a.dst, lab, first_tile, a.tiles_per_task, 1, a.m,
-                                                        a.n, order, rerr);
+    const bool pred = run_tiles_lab<EPT, BLOCK, ATOMIC, WindowLabels, (EPT <= 2 ? 4 : 2)>(
+        a.src, a.dst, lab, first_tile, a.tiles_per_task, 1, a.m, a.n, order, rerr);
     __syncthreads();
     for (unsigned i = threadIdx.x; i < cnt; i += BLOCK)
         if ((dirty[i >> 5] >> (i & 31)) & 1u) put<ATOMIC>(a.L, (int)(lo + i), wl[i]);

@@ -125,6 +125,7 @@ int resolve_opts(const contour_opts_t* o, Resolved* r)
         return CONTOUR_EINVAL;
     if (o->chunk_tiles < 0 || o->grid < 0) return CONTOUR_EINVAL;
     if (o->reorder < CONTOUR_REORDER_AUTO || o->reorder > CONTOUR_REORDER_ON) return CONTOUR_EINVAL;
+    if (o->window != 0 && o->window < 1024) return CONTOUR_EINVAL;
     // Algorithm 1 applies its conditional assignments to L_u with the
     // compare-and-swap loop of Eq. (cas); the synchronous update is only
     // offered that way, and sequenced from the host.
@@ -144,6 +145,7 @@ int resolve_opts(const contour_opts_t* o, Resolved* r)
     r->chunk_tiles = o->chunk_tiles;
     r->grid = o->grid;
     r->reorder = o->reorder;
+    r->window = o->window;
     return CONTOUR_OK;
 }
 
@@ -167,6 +169,7 @@ void contour_default_opts(contour_opts_t* opts)
     opts->chunk_tiles = 0;
     opts->grid = 0;
     opts->reorder = CONTOUR_REORDER_AUTO;
+    opts->window = 0;
 }
 
 const char* contour_status_string(int s)

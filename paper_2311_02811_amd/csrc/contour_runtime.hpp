@@ -62,6 +62,7 @@ struct Resolved {
     int chunk_tiles;
     int grid;
     int reorder;
+    int window;
 };
 
 // Wall-clock ticks a single solve may run before the watchdog stops it
