@@ -68,7 +68,8 @@ struct SolveArgs {
     long long m;
     unsigned n;
     long long tasks;     // persistent driver: tasks per sweep
-    int tiles_per_task;  // persistent driver
+    long long ntiles;    // persistent driver: tiles of BLOCK * EPT edges per sweep
+    int tiles_per_task;  // persistent driver: the largest task, in tiles
     Sched sched;
     int max_sweeps;      // 0 = no limit
     Ctl* ctl;
@@ -92,9 +93,9 @@ __device__ __forceinline__ void put(int* L, int x, int z)
 }
 
 // ---------------------------------------------------------------------------
-// Edge tile: BLOCK * EPT consecutive edges starting at `base`; thread t owns
-// edges base + k * BLOCK + t (k < EPT), so every load instruction of a wave
-// reads 256 contiguous bytes.  All first-level gathers of a thread are issued
+// Edge tile: BLOCK * EPT consecutive edges starting at `base`, EPT per
+// thread, read so that every load instruction of a wave covers contiguous
+// bytes.  All first-level gathers of a thread are issued
 // before any second-level gather, and all gathers before any store.
 // R is the array read, W the array written; they are the same array for the
 // asynchronous update and differ for the synchronous one (Algorithm 1).
@@ -102,14 +103,44 @@ __device__ __forceinline__ void put(int* L, int x, int z)
 // when an edge id is outside [0, n) (that edge is skipped).
 // ---------------------------------------------------------------------------
 
+typedef int edge2_t __attribute__((ext_vector_type(2)));
+typedef int edge4_t __attribute__((ext_vector_type(4)));
+
 template <int EPT, int BLOCK>
 __device__ __forceinline__ void fetch_tile(const int* __restrict__ src, const int* __restrict__ dst,
                                            long long base, long long m, int (&w)[EPT], int (&v)[EPT],
                                            bool (&ok)[EPT])
 {
-    // Loads are unconditional (an edge past the end re-reads edge m-1) so
-    // that every load of the tile is in flight at once instead of each
-    // waiting behind a branch.
+    // A whole tile with 8- or 16-byte aligned arrays: thread t takes EPT
+    // consecutive edges with one vector load per array (fewer memory
+    // instructions for the address unit to process).  Both conditions are
+    // the same for every lane.
+    constexpr int VW = EPT % 4 == 0 ? 4 : EPT % 2 == 0 ? 2 : 1;
+    if (VW > 1 && base + (long long)BLOCK * EPT <= m &&
+        ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & (VW * 4 - 1)) == 0) {
+        const long long e0 = base + (long long)threadIdx.x * EPT;
+#pragma unroll
+        for (int j = 0; j < EPT / VW; ++j) {
+            if (VW == 4) {
+                const edge4_t a = __builtin_nontemporal_load(reinterpret_cast<const edge4_t*>(src + e0) + j);
+                const edge4_t b = __builtin_nontemporal_load(reinterpret_cast<const edge4_t*>(dst + e0) + j);
+                w[4 * j] = a.x, w[4 * j + 1] = a.y, w[4 * j + 2] = a.z, w[4 * j + 3] = a.w;
+                v[4 * j] = b.x, v[4 * j + 1] = b.y, v[4 * j + 2] = b.z, v[4 * j + 3] = b.w;
+            } else {
+                const edge2_t a = __builtin_nontemporal_load(reinterpret_cast<const edge2_t*>(src + e0) + j);
+                const edge2_t b = __builtin_nontemporal_load(reinterpret_cast<const edge2_t*>(dst + e0) + j);
+                w[2 * j] = a.x, w[2 * j + 1] = a.y;
+                v[2 * j] = b.x, v[2 * j + 1] = b.y;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) ok[k] = true;
+        return;
+    }
+    // Otherwise thread t takes edges base + k * BLOCK + t.  Loads are
+    // unconditional (an edge past the end re-reads edge m-1) so that every
+    // load of the tile is in flight at once instead of each waiting behind a
+    // branch.
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
         const long long e = base + (long long)k * BLOCK + threadIdx.x;
@@ -376,17 +407,44 @@ struct FlatLabels {
 // outside it are read and written in global memory G.  Stores into the
 // window mark a dirty bit, and the workgroup writes the dirty labels back
 // once at the end of its task.
+//
+// A gather issues an LDS read (clamped index) and, unless every lane of the
+// wave reads inside the window, a buffer load of G whose offset is pushed out
+// of the buffer's range for the lanes inside the window: the hardware range
+// check turns those lanes into no-ops that return 0, and a select keeps the
+// right value.  The only branch is wave-uniform, so all gathers of a tile
+// stay in flight together, and a wave whose gathers all hit the window waits
+// on LDS only, not behind its own edge prefetches (vector memory loads
+// complete in order).  An ordinary load of G under a per-lane branch would
+// be merged with the LDS read into one flat load, or write the same register
+// and wait for it.  Buffer offsets are 32-bit bytes, so label windows are
+// only used for n < 2^30 (a host-side rule).
+constexpr unsigned kBufferDataFormat32 = 4u << 15;  // buffer resource word 3: 32-bit elements
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t label_buffer(const int* G, unsigned n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<int*>(G), (short)0, (int)(n * 4u),
+                                             (int)kBufferDataFormat32);
+}
+
 struct WindowLabels {
     int* lds;
     unsigned* dirty;
     unsigned lo;
     unsigned cnt;
     int* G;
+    __amdgpu_buffer_rsrc_t rsrc;
+    unsigned oob;  // a byte offset past the end of G: 4 n
     __device__ __forceinline__ int ld(int x) const
     {
+        typedef __attribute__((address_space(3))) const int* lds_ptr;
         const unsigned i = (unsigned)x - lo;
-        if (i < cnt) return lds[i];
-        return G[x];
+        const bool in = i < cnt;
+        const int vl = ((lds_ptr)lds)[in ? i : 0];
+        int vg = 0;
+        if (__builtin_amdgcn_ballot_w64(!in) != 0)  // wave-uniform: skipped when every id is in the window
+            vg = __builtin_amdgcn_raw_buffer_load_b32(rsrc, in ? oob : (unsigned)x * 4u, 0, 0);
+        return in ? vl : vg;
     }
     template <bool ATOMIC>
     __device__ __forceinline__ void st(int x, int z) const

@@ -45,67 +45,143 @@ __device__ __forceinline__ void persistent_publish(const SolveArgs& a, Persisten
     w.err = 0;
 }
 
-// Thread 0 only: take the next task of the graph and decide whether the
-// workgroup works on it.
-__device__ __forceinline__ void persistent_next(const SolveArgs& a, PersistentState& w, int* go_out,
-                                                long long* task_out)
+// Thread 0 only: take the next task of the graph (-1 once the solve has
+// ended).
+__device__ __forceinline__ long long persistent_take(const SolveArgs& a)
 {
     Ctl* c = a.ctl;
-    int go = 0;
-    long long t = 0;
-    if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ST_RUNNING) {
-        t = (long long)__hip_atomic_fetch_add(&c->next_task, 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const long long sweep = t / a.tasks;
-        if (sweep != w.sweep) {
-            // leaving w.sweep for good: publish it before waiting on sweep - 1
-            persistent_publish(a, w);
-            if (sweep > 0) {
-                const unsigned long long need = (unsigned long long)(sweep * a.tasks);
-                while (__hip_atomic_load(&c->done_task, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                    if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ST_RUNNING)
-                        break;
-                    if (watchdog_expired(c, a.watchdog)) {
-                        int expect = ST_RUNNING;
-                        __hip_atomic_compare_exchange_strong(&c->state, &expect, (int)ST_TIMEOUT, __ATOMIC_RELAXED,
-                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(2);
-                }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            }
-            w.sweep = sweep;
-        }
-        if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ST_RUNNING) {
-            const int lc = __hip_atomic_load(&c->last_change, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            int st = ST_RUNNING;
-            if (sweep > 0 && lc <= sweep - 1)
-                st = ST_CONVERGED;
-            else if (a.max_sweeps > 0 && sweep >= a.max_sweeps)
-                st = ST_LIMIT;
-            else if (watchdog_expired(c, a.watchdog))
-                st = ST_TIMEOUT;
-            if (st == ST_RUNNING) {
-                go = 1;
-            } else {
-                int expect = ST_RUNNING;
-                if (__hip_atomic_compare_exchange_strong(&c->state, &expect, st, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT))
-                    __hip_atomic_store(&c->sweeps, (int)sweep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-    }
-    *go_out = go;
-    *task_out = t;
+    if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ST_RUNNING) return -1;
+    return (long long)__hip_atomic_fetch_add(&c->next_task, 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// The loop keeps every thread-0 section inside one if-region at the end of
-// the body (plus one before the loop), so all lanes of every wave pass the
-// same barriers in the same order.  The convergence decision reads
-// last_change only after done_task shows every task of the previous sweep
-// published, and each publication adds to done_task with release semantics
-// after its last_change update, so a sweep that changed a label is never
-// mistaken for one that did not.
+// Thread 0 only: start task t (t < 0: the workgroup leaves) and decide
+// whether the workgroup works on it.  A task of a later sweep than the last
+// one first publishes the workgroup's completed tasks and then waits until
+// the previous sweep is complete.
+__device__ __forceinline__ int persistent_begin(const SolveArgs& a, PersistentState& w, long long t)
+{
+    Ctl* c = a.ctl;
+    if (t < 0) return 0;
+    int go = 0;
+    const long long sweep = t / a.tasks;
+    if (sweep != w.sweep) {
+        // leaving w.sweep for good: publish it before waiting on sweep - 1
+        persistent_publish(a, w);
+        if (sweep > 0) {
+            const unsigned long long need = (unsigned long long)(sweep * a.tasks);
+            while (__hip_atomic_load(&c->done_task, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ST_RUNNING)
+                    break;
+                if (watchdog_expired(c, a.watchdog)) {
+                    int expect = ST_RUNNING;
+                    __hip_atomic_compare_exchange_strong(&c->state, &expect, (int)ST_TIMEOUT, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        w.sweep = sweep;
+    }
+    if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ST_RUNNING) {
+        const int lc = __hip_atomic_load(&c->last_change, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int st = ST_RUNNING;
+        if (sweep > 0 && lc <= sweep - 1)
+            st = ST_CONVERGED;
+        else if (a.max_sweeps > 0 && sweep >= a.max_sweeps)
+            st = ST_LIMIT;
+        else if (watchdog_expired(c, a.watchdog))
+            st = ST_TIMEOUT;
+        if (st == ST_RUNNING) {
+            go = 1;
+        } else {
+            int expect = ST_RUNNING;
+            if (__hip_atomic_compare_exchange_strong(&c->state, &expect, st, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT))
+                __hip_atomic_store(&c->sweeps, (int)sweep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    return go;
+}
+
+// Task `chunk` of a sweep covers tiles [first, first + count): the sweep's
+// tiles split evenly over the tasks (sizes differ by at most one tile), and
+// the host makes the number of tasks a multiple of the resident workgroups,
+// so the workgroups finish a sweep together.
+__device__ __forceinline__ void task_tiles(const SolveArgs& a, long long chunk, long long* first, long long* count)
+{
+    const long long f = chunk * a.ntiles / a.tasks;
+    *first = f;
+    *count = (chunk + 1) * a.ntiles / a.tasks - f;
+}
+
+// Stage cnt labels from global memory g into LDS w.  Every thread keeps
+// kStageUnroll loads in flight before it writes any of them to LDS, 16 bytes
+// each when g is 16-byte aligned, so one workgroup has up to 64 KiB of label
+// reads outstanding instead of one 4-byte read per thread at a time.  Loads
+// and LDS writes are unconditional (indices past the end are clamped to the
+// last element, which then receives its own value several times) so that the
+// compiler cannot sink a load into a branch and wait for it there.
+constexpr int kStageUnroll = 4;
+
+template <int BLOCK>
+__device__ __forceinline__ void stage_window(int* w, const int* g, unsigned cnt)
+{
+    unsigned done = 0;
+    if ((reinterpret_cast<uintptr_t>(g) & 15) == 0 && cnt >= 4) {
+        const unsigned q = cnt >> 2;
+        const int4* g4 = reinterpret_cast<const int4*>(g);
+        int4* w4 = reinterpret_cast<int4*>(w);
+        for (unsigned i0 = threadIdx.x; i0 < q; i0 += BLOCK * kStageUnroll) {
+            int4 v[kStageUnroll];
+#pragma unroll
+            for (int u = 0; u < kStageUnroll; ++u) v[u] = g4[min(i0 + u * BLOCK, q - 1)];
+#pragma unroll
+            for (int u = 0; u < kStageUnroll; ++u) w4[min(i0 + u * BLOCK, q - 1)] = v[u];
+        }
+        done = q << 2;
+    }
+    for (unsigned i0 = done + threadIdx.x; i0 < cnt; i0 += BLOCK * kStageUnroll) {
+        int v[kStageUnroll];
+#pragma unroll
+        for (int u = 0; u < kStageUnroll; ++u) v[u] = g[min(i0 + u * BLOCK, cnt - 1)];
+#pragma unroll
+        for (int u = 0; u < kStageUnroll; ++u) w[min(i0 + u * BLOCK, cnt - 1)] = v[u];
+    }
+}
+
+// Write the labels of window w whose dirty bit is set back to g (plain or
+// atomic-minimum stores, as the write mode says).  Each thread handles four
+// consecutive labels per step (one 16-byte LDS read; the window's LDS holds a
+// multiple of 32 labels, so the read stays inside it) and kStageUnroll steps
+// at a time.
+template <int BLOCK, bool ATOMIC>
+__device__ __forceinline__ void write_back_window(const int* w, const unsigned* dirty, int* g, unsigned cnt)
+{
+    const unsigned q = (cnt + 3) >> 2;
+    const int4* w4 = reinterpret_cast<const int4*>(w);
+    for (unsigned i0 = threadIdx.x; i0 < q; i0 += BLOCK * kStageUnroll) {
+        unsigned bits[kStageUnroll];
+        int4 val[kStageUnroll];
+#pragma unroll
+        for (int u = 0; u < kStageUnroll; ++u) {
+            const unsigned idx = min(i0 + u * BLOCK, q - 1);
+            const unsigned j = idx * 4;
+            bits[u] = i0 + u * BLOCK < q ? (dirty[j >> 5] >> (j & 31)) & 15u : 0u;
+            val[u] = w4[idx];
+        }
+#pragma unroll
+        for (int u = 0; u < kStageUnroll; ++u) {
+            const int j = (int)(i0 + u * BLOCK) * 4;
+            if (bits[u] & 1u) put<ATOMIC>(g, j, val[u].x);
+            if (bits[u] & 2u) put<ATOMIC>(g, j + 1, val[u].y);
+            if (bits[u] & 4u) put<ATOMIC>(g, j + 2, val[u].z);
+            if (bits[u] & 8u) put<ATOMIC>(g, j + 3, val[u].w);
+        }
+    }
+}
+
 // Windowed task (edges grouped by source block): stage the labels of the
 // task's source blocks, plus a margin, in LDS; gather and store there for
 // ids inside the window and in global memory otherwise; write the labels the
@@ -115,16 +191,19 @@ __device__ __forceinline__ void persistent_next(const SolveArgs& a, PersistentSt
 // than a value the location held during the sweep, exactly as for a direct
 // store.
 template <int EPT, int BLOCK, bool ATOMIC>
-__device__ __forceinline__ bool window_task(const SolveArgs& a, long long first_tile, int order, int& rerr)
+__device__ __forceinline__ bool window_task(const SolveArgs& a, long long first_tile, long long count, int order,
+                                            int& rerr)
 {
-    extern __shared__ int dyn_lds[];
+    extern __shared__ __align__(16) int dyn_lds[];
     __shared__ unsigned s_lo, s_cnt;
     const long long tile_edges = (long long)BLOCK * EPT;
     if (threadIdx.x == 0) {
         const long long e0 = first_tile * tile_edges;
-        const long long e1 = std::min(a.m, e0 + (long long)a.tiles_per_task * tile_edges) - 1;
+        const long long e1 = std::min(a.m, e0 + count * tile_edges) - 1;
         const unsigned f = (unsigned)a.src[e0], l = (unsigned)a.src[e1];
-        const unsigned lo = f < a.n ? (f >> a.win_shift) << a.win_shift : 0u;
+        // lo rounded down to a multiple of 4 so that the window is staged
+        // with 16-byte loads
+        const unsigned lo = f < a.n ? ((f >> a.win_shift) << a.win_shift) & ~3u : 0u;
         unsigned long long hi = l < a.n ? ((unsigned long long)((l >> a.win_shift) + 1) << a.win_shift) : a.n;
         hi = std::min<unsigned long long>(a.n, hi + (unsigned)a.win_margin);
         s_lo = lo;
@@ -135,47 +214,74 @@ __device__ __forceinline__ bool window_task(const SolveArgs& a, long long first_
     const unsigned cnt = uniform((int)s_cnt);
     int* wl = dyn_lds;
     unsigned* dirty = reinterpret_cast<unsigned*>(dyn_lds + a.win_cap);
-    for (unsigned i = threadIdx.x; i < cnt; i += BLOCK) wl[i] = a.L[lo + i];
+    stage_window<BLOCK>(wl, a.L + lo, cnt);
     for (unsigned i = threadIdx.x; i < (cnt + 31) / 32; i += BLOCK) dirty[i] = 0;
     __syncthreads();
-    const WindowLabels lab{wl, dirty, lo, cnt, a.L};
-    const bool pred = run_tiles_lab<EPT, BLOCK, ATOMIC, WindowLabels, (EPT <= 2 ? 4 : 2)>(
-        a.src, a.dst, lab, first_tile, a.tiles_per_task, 1, a.m, a.n, order, rerr);
+    const WindowLabels lab{wl, dirty, lo, cnt, a.L, label_buffer(a.L, a.n), a.n * 4u};
+    const bool pred = run_tiles_lab<EPT, BLOCK, ATOMIC, WindowLabels, 1>(
+        a.src, a.dst, lab, first_tile, count, 1, a.m, a.n, order, rerr);
     __syncthreads();
-    for (unsigned i = threadIdx.x; i < cnt; i += BLOCK)
-        if ((dirty[i >> 5] >> (i & 31)) & 1u) put<ATOMIC>(a.L, (int)(lo + i), wl[i]);
+    write_back_window<BLOCK, ATOMIC>(wl, dirty, a.L + lo, cnt);
     return pred;
 }
 
+// The task loop.  Its thread-0 sections (take a task; begin it, which may
+// spin) each end at a barrier, and all loop control is read back from LDS
+// through readfirstlane, so every lane of a wave passes the same barriers in
+// the same order.  The convergence decision reads last_change only after
+// done_task shows every task of the previous sweep published, and each
+// publication adds to done_task with release semantics after its
+// last_change update, so a sweep that changed a label is never mistaken for
+// one that did not.
 template <int EPT, int BLOCK, bool ATOMIC, bool WIN = false>
 __device__ __forceinline__ void persistent_solve(const SolveArgs& a)
 {
     __shared__ long long s_task;
     __shared__ int s_go;
     PersistentState w{-1, 0, 0, 0};
-    if (threadIdx.x == 0) persistent_next(a, w, &s_go, &s_task);
+    if (threadIdx.x == 0) {
+        const long long t = persistent_take(a);
+        s_go = persistent_begin(a, w, t);
+        s_task = t;
+    }
     __syncthreads();
+    // per thread: some task since the last publication changed a label /
+    // met an out-of-range id
+    int changed = 0, rerr = 0;
     for (;;) {
         if (!uniform(s_go)) break;
         const long long t = uniform(s_task);
         const long long sweep = t / a.tasks;
-        const long long chunk = t - sweep * a.tasks;
+        long long first, count;
+        task_tiles(a, t - sweep * a.tasks, &first, &count);
         const int order = order_of_sweep(a.sched, (int)sweep);
-        int rerr = 0;
         bool pred;
         if (WIN)
-            pred = window_task<EPT, BLOCK, ATOMIC>(a, chunk * a.tiles_per_task, order, rerr);
+            pred = window_task<EPT, BLOCK, ATOMIC>(a, first, count, order, rerr);
         else
-            pred = run_tiles_order<EPT, BLOCK, ATOMIC>(a.src, a.dst, a.L, a.L, chunk * a.tiles_per_task,
-                                                       a.tiles_per_task, 1, a.m, a.n, order, rerr);
-        drain_stores();
-        const int any = __syncthreads_or(pred ? 1 : 0);
-        const int anyerr = __syncthreads_or(rerr);
+            pred = run_tiles_order<EPT, BLOCK, ATOMIC>(a.src, a.dst, a.L, a.L, first, count, 1, a.m, a.n, order,
+                                                       rerr);
+        changed |= pred ? 1 : 0;
+        // take the next task; only a move to another sweep (or the end)
+        // publishes, which needs every store of the workgroup drained and
+        // the per-thread flags combined
+        if (threadIdx.x == 0) s_task = persistent_take(a);
+        __syncthreads();
+        const long long next = uniform(s_task);
+        const bool leave = next < 0 || next / a.tasks != sweep;
+        int any = 0, anyerr = 0;
+        if (leave) {
+            drain_stores();
+            any = __syncthreads_or(changed);
+            anyerr = __syncthreads_or(rerr);
+            changed = 0;
+            rerr = 0;
+        }
         if (threadIdx.x == 0) {
             w.pending += 1;
             w.changed |= any;
             w.err |= anyerr;
-            persistent_next(a, w, &s_go, &s_task);
+            s_go = persistent_begin(a, w, next);
         }
         __syncthreads();
     }

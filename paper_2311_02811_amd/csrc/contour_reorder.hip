@@ -12,11 +12,12 @@
 //            counts[d * G + g] (digit-major);
 //   scan     an exclusive prefix sum of that matrix gives workgroup g the
 //            first output slot of each digit;
-//   scatter  workgroup g loads its chunk into LDS, orders it by digit there
+//   scatter  workgroup g loads its chunk into LDS, ranks it by digit there
 //            (stable: each thread owns eight consecutive edges and a column
-//            of per-digit counters), and writes each digit's run to its
-//            slots.  A run holds 64 edges on average, so the stores are
-//            whole cache lines rather than scattered words.
+//            of per-digit counters), places it in rank order in LDS, and
+//            then writes it out with consecutive lanes on consecutive
+//            ranks, so each digit's run (64 edges on average) is stored as
+//            contiguous words rather than scattered ones.
 // An id outside [0, n) goes to the last block unchanged; the sweep's own
 // range check rejects it.
 #include <hip/hip_runtime.h>
@@ -66,7 +67,12 @@ __global__ __launch_bounds__(kRxThreads) void k_rx_count(const int* __restrict__
     const long long c = chunk_of(blockIdx.x, gridDim.x);
     const long long e0 = c * kRxChunk;
     const int len = (int)std::min<long long>(kRxChunk, m - e0);
-    for (int i = threadIdx.x; i < len; i += kRxThreads) atomicAdd(&h[digit_of(ld_edge(src + e0 + i), shift, K, pass)], 1);
+    int w[kRxPer];
+#pragma unroll
+    for (int k = 0; k < kRxPer; ++k) w[k] = ld_edge(src + e0 + min(k * kRxThreads + (int)threadIdx.x, len - 1));
+#pragma unroll
+    for (int k = 0; k < kRxPer; ++k)
+        if (k * kRxThreads + (int)threadIdx.x < len) atomicAdd(&h[digit_of(w[k], shift, K, pass)], 1);
     __syncthreads();
     if (threadIdx.x < kDigits) counts[(long long)threadIdx.x * gridDim.x + c] = h[threadIdx.x];
 }
@@ -138,42 +144,67 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(int* a, long long len
         if (base + i < len) a[base + i] += add;
 }
 
+// Counter matrix of the scatter, cnt[d * threads + t], stored with one
+// padding word after every 32 so that a thread walking 32 consecutive
+// entries and its neighbours walking theirs hit different LDS banks.
+__device__ __forceinline__ int padded(int i) { return i + (i >> 5); }
+static constexpr int kRxCells = kDigits * kRxThreads;
+static constexpr int kRxCellsPadded = kRxCells + kRxCells / 32;
+
 __global__ __launch_bounds__(kRxThreads) void k_rx_scatter(const int* __restrict__ src, const int* __restrict__ dst,
                                                            long long m, int shift, int K, int pass,
                                                            const int* __restrict__ offsets, int* __restrict__ osrc,
                                                            int* __restrict__ odst)
 {
     __shared__ int in_s[kRxChunk], in_d[kRxChunk];
-    __shared__ int cnt[kDigits * kRxThreads];  // cnt[d * threads + t]
+    // the counters, later reused for the output slot of each sorted edge
+    __shared__ int cnt[kRxCellsPadded];
     __shared__ int tot[kRxThreads];
     __shared__ int dstart[kDigits];
-    __shared__ long long gbase[kDigits];
+    __shared__ int gbase[kDigits];
     const int t = threadIdx.x;
     const long long c = chunk_of(blockIdx.x, gridDim.x);
     const long long e0 = c * kRxChunk;
     const int len = (int)std::min<long long>(kRxChunk, m - e0);
-    for (int i = t; i < len; i += kRxThreads) {
-        in_s[i] = ld_edge(src + e0 + i);
-        in_d[i] = ld_edge(dst + e0 + i);
+    {
+        // every load of the chunk in flight at once (indices past the end
+        // re-read the last edge and store it again in its own slot)
+        int vs[kRxPer], vd[kRxPer];
+#pragma unroll
+        for (int k = 0; k < kRxPer; ++k) {
+            const int i = min(k * kRxThreads + t, len - 1);
+            vs[k] = ld_edge(src + e0 + i);
+            vd[k] = ld_edge(dst + e0 + i);
+        }
+#pragma unroll
+        for (int k = 0; k < kRxPer; ++k) {
+            const int i = min(k * kRxThreads + t, len - 1);
+            in_s[i] = vs[k];
+            in_d[i] = vd[k];
+        }
     }
-    for (int i = t; i < kDigits * kRxThreads; i += kRxThreads) cnt[i] = 0;
+    for (int i = t; i < kRxCellsPadded; i += kRxThreads) cnt[i] = 0;
+    // output slots fit int32: reordering is only used for m < 2^31
     if (t < kDigits) gbase[t] = offsets[(long long)t * gridDim.x + c];
     __syncthreads();
     // thread t owns edges [t * kRxPer, (t + 1) * kRxPer) of the chunk
-    int dig[kRxPer];
+    int es[kRxPer], ed[kRxPer], dig[kRxPer], rank[kRxPer];
 #pragma unroll
     for (int k = 0; k < kRxPer; ++k) {
         const int i = t * kRxPer + k;
-        dig[k] = i < len ? digit_of(in_s[i], shift, K, pass) : -1;
-        if (dig[k] >= 0) cnt[dig[k] * kRxThreads + t] += 1;
+        es[k] = in_s[min(i, len - 1)];
+        ed[k] = in_d[min(i, len - 1)];
+        dig[k] = i < len ? digit_of(es[k], shift, K, pass) : -1;
+        if (dig[k] >= 0) cnt[padded(dig[k] * kRxThreads + t)] += 1;
     }
     __syncthreads();
     // exclusive scan of cnt in digit-major order: thread t scans entries
     // [t * 32, t * 32 + 32), then the thread totals are scanned
     int run = 0;
     for (int k = 0; k < kDigits; ++k) {
-        const int x = cnt[t * kDigits + k];
-        cnt[t * kDigits + k] = run;
+        const int j = padded(t * kDigits + k);
+        const int x = cnt[j];
+        cnt[j] = run;
         run += x;
     }
     tot[t] = run;
@@ -185,24 +216,34 @@ __global__ __launch_bounds__(kRxThreads) void k_rx_scatter(const int* __restrict
         __syncthreads();
     }
     const int add = t ? tot[t - 1] : 0;
-    for (int k = 0; k < kDigits; ++k) cnt[t * kDigits + k] += add;
+    for (int k = 0; k < kDigits; ++k) cnt[padded(t * kDigits + k)] += add;
     __syncthreads();
     // cnt[d * threads + t] is now the chunk-local rank of thread t's first
-    // digit-d edge, and digit d's run starts at rank dstart[d].  Each thread
-    // writes its edges straight to their slots, in order (stable), moving
-    // only its own counters.
-    if (t < kDigits) dstart[t] = cnt[t * kRxThreads];
+    // digit-d edge (stable order), and digit d's run starts at rank
+    // dstart[d]
+    if (t < kDigits) dstart[t] = cnt[padded(t * kRxThreads)];
     __syncthreads();
 #pragma unroll
+    for (int k = 0; k < kRxPer; ++k)
+        rank[k] = dig[k] >= 0 ? cnt[padded(dig[k] * kRxThreads + t)]++ : 0;
+    __syncthreads();
+    // place the chunk in rank order in LDS, with each edge's output slot
+    // (its digit's run start plus its offset in the run) in cnt
+#pragma unroll
     for (int k = 0; k < kRxPer; ++k) {
-        const int i = t * kRxPer + k;
         if (dig[k] >= 0) {
-            const int d = dig[k];
-            const int r = cnt[d * kRxThreads + t]++;
-            const long long idx = gbase[d] + (r - dstart[d]);
-            osrc[idx] = in_s[i];
-            odst[idx] = in_d[i];
+            in_s[rank[k]] = es[k];
+            in_d[rank[k]] = ed[k];
+            cnt[rank[k]] = gbase[dig[k]] + (rank[k] - dstart[dig[k]]);
         }
+    }
+    __syncthreads();
+    // consecutive lanes write consecutive ranks: each digit's run is stored
+    // as contiguous words
+    for (int i = t; i < len; i += kRxThreads) {
+        const int slot = cnt[i];
+        osrc[slot] = in_s[i];
+        odst[slot] = in_d[i];
     }
 }
 
@@ -221,16 +262,20 @@ void reorder_geometry(const DeviceInfo& d, long long m, int n, Reorder* r)
     const long long cells = (long long)kDigits * r->G;
     r->nblk = (int)((cells + kScanSegment - 1) / kScanSegment);
     r->m = m;
-    r->elems = 4 * m + cells + r->nblk;
+    // every array starts on a 16-byte boundary (the sweep reads edges with
+    // 16-byte loads when it can)
+    const long long mp = (m + 3) & ~3LL;
+    r->elems = 4 * mp + cells + ((r->nblk + 3) & ~3);
 }
 
 void reorder_bind(Reorder* r, int* ws)
 {
+    const long long mp = (r->m + 3) & ~3LL;
     r->src2 = ws;
-    r->dst2 = ws + r->m;
-    r->tmp_src = ws + 2 * r->m;
-    r->tmp_dst = ws + 3 * r->m;
-    r->counts = ws + 4 * r->m;
+    r->dst2 = ws + mp;
+    r->tmp_src = ws + 2 * mp;
+    r->tmp_dst = ws + 3 * mp;
+    r->counts = ws + 4 * mp;
     r->sums = r->counts + (long long)kDigits * r->G;
 }
 

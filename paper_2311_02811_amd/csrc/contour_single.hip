@@ -121,13 +121,12 @@ typedef void (*sweep_fn)(SolveArgs, const int*, int*, int);
 
 // Register limits: 1024-thread workgroups get at most 128 registers per
 // lane and 512-thread ones 256.  Edges per thread of the persistent loop are
-// capped where the compiler would otherwise spill: eight become four (1024
-// threads, or 512 with a label window), and with a label window 1024-thread
-// workgroups take at most two.
+// capped where the compiler would otherwise spill: eight become four with
+// 1024 threads.
 template <int BLOCK, bool WIN>
 struct EptCap {
-    static constexpr int e8 = (BLOCK == 1024 || (BLOCK == 512 && WIN)) ? 4 : 8;
-    static constexpr int e4 = (BLOCK == 1024 && WIN) ? 2 : 4;
+    static constexpr int e8 = BLOCK == 1024 ? 4 : 8;
+    static constexpr int e4 = 4;
 };
 
 template <int BLOCK, bool ATOMIC, bool WIN>
@@ -231,6 +230,7 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
     a.watchdog = watchdog_ticks(d);
     a.tiles_per_task = 1;
     a.tasks = 0;
+    a.ntiles = 0;
     a.win_cap = 0;
     a.win_shift = 0;
     a.win_margin = 0;
@@ -239,7 +239,8 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
     p.lds = 0;
     if (m > 0) {
         sweep_fn ks;
-        const bool win = p.reorder;
+        // label windows read global labels through 32-bit buffer offsets
+        const bool win = p.reorder && n < (1 << 30);
         pick_kernels(r.block, r.ept, r.atomic, &p.kernel, &ks, win);
         if (win) {
             // the largest window (labels + one dirty bit each) that fits the
@@ -265,9 +266,15 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
             const long long want = std::max<long long>(32768, std::min<long long>(262144, m / 1024));
             tpt = (int)std::max<long long>(1, want / tile_edges);
         }
-        a.tiles_per_task = tpt;
-        a.tasks = (ntiles + tpt - 1) / tpt;
-        p.grid = (unsigned)(r.grid ? r.grid : std::min<long long>(resident, a.tasks));
+        // the sweep's tiles split evenly over a number of tasks that is a
+        // multiple of the workgroups, so that they finish a sweep together
+        const long long g = r.grid ? r.grid : resident;
+        long long tasks = (ntiles + tpt - 1) / tpt;
+        if (tasks > g) tasks = std::min<long long>(ntiles, (tasks + g - 1) / g * g);
+        a.ntiles = ntiles;
+        a.tasks = tasks;
+        a.tiles_per_task = (int)((ntiles + tasks - 1) / tasks);
+        p.grid = (unsigned)std::min<long long>(g, a.tasks);
     }
     *out = p;
     return CONTOUR_OK;
@@ -354,6 +361,7 @@ static int run_hostloop(const DeviceInfo& d, const Resolved& r0, const int* src,
         const long long ntiles = (m + tile_edges - 1) / tile_edges;
         a.tiles_per_task = 1;
         a.tasks = ntiles;
+        a.ntiles = ntiles;
         const long long grid = r.grid ? r.grid : std::min<long long>(ntiles, (long long)d.cus * 16);
         int* other = r.sync ? ws->scratch + (reorder ? ro.elems : 0) : nullptr;
         int sweep = 0, ahead = 4;
