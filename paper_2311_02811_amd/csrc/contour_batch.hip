@@ -504,8 +504,9 @@ static int create_plan(const contour_batch_t* b, const contour_opts_t* opts, con
                 free_plan(p);
                 return rr;
             }
-            graphs.push_back(pl.args);
             long long w = std::max<long long>(1, std::min<long long>(resident, (pl.args.tasks + 3) / 4));
+            pl.args.take = (int)std::max<long long>(1, pl.args.tasks / w);
+            graphs.push_back(pl.args);
             want.push_back((int)w);
             sum_want += w;
             max_n = std::max(max_n, pl.args.n);

@@ -70,6 +70,7 @@ struct SolveArgs {
     long long tasks;     // persistent driver: tasks per sweep
     long long ntiles;    // persistent driver: tiles of BLOCK * EPT edges per sweep
     int tiles_per_task;  // persistent driver: the largest task, in tiles
+    int take;            // persistent driver: tasks a workgroup takes at once (>= 1)
     Sched sched;
     int max_sweeps;      // 0 = no limit
     Ctl* ctl;

@@ -26,10 +26,11 @@ namespace contour {
 // be complete.  A workgroup therefore issues one release, one done_task
 // add and one acquire per sweep it takes part in, instead of one per task.
 struct PersistentState {
-    long long sweep;    // sweep of the last task taken (-1: none yet)
-    int pending;        // tasks of that sweep completed but not yet published
-    int changed;        // some published-later task changed a label
-    int err;            // some task met an out-of-range id
+    long long sweep;         // sweep of the last task taken (-1: none yet)
+    int pending;             // tasks of that sweep completed but not yet published
+    int changed;             // some published-later task changed a label
+    int err;                 // some task met an out-of-range id
+    unsigned long long t0;   // the solve's start on the wall clock (Ctl::t0)
 };
 
 __device__ __forceinline__ void persistent_publish(const SolveArgs& a, PersistentState& w)
@@ -46,12 +47,25 @@ __device__ __forceinline__ void persistent_publish(const SolveArgs& a, Persisten
 }
 
 // Thread 0 only: take the next task of the graph (-1 once the solve has
-// ended).
-__device__ __forceinline__ long long persistent_take(const SolveArgs& a)
+// ended).  Tasks are taken from the graph's counter in groups of a.take
+// consecutive tasks (the host sets a group to about one workgroup's share of
+// a sweep), so a workgroup pays the latency of one device-wide atomic per
+// group rather than per task; [*grp, *grp_end) is what remains of the
+// workgroup's current group.
+__device__ __forceinline__ long long persistent_take(const SolveArgs& a, long long* grp, long long* grp_end)
 {
     Ctl* c = a.ctl;
+    // the rest of a group needs no memory access; the solve's state is read
+    // when a new group is taken and whenever a task starts a new sweep
+    if (*grp < *grp_end) return (*grp)++;
     if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ST_RUNNING) return -1;
-    return (long long)__hip_atomic_fetch_add(&c->next_task, 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long k = a.take > 1 ? a.take : 1;
+    const long long t =
+        (long long)__hip_atomic_fetch_add(&c->next_task, (unsigned long long)k, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+    *grp = t + 1;
+    *grp_end = t + k;
+    return t;
 }
 
 // Thread 0 only: start task t (t < 0: the workgroup leaves) and decide
@@ -62,9 +76,21 @@ __device__ __forceinline__ int persistent_begin(const SolveArgs& a, PersistentSt
 {
     Ctl* c = a.ctl;
     if (t < 0) return 0;
-    int go = 0;
     const long long sweep = t / a.tasks;
-    if (sweep != w.sweep) {
+    // Another task of the sweep already begun: the sweep was found running
+    // then, and neither convergence nor the sweep limit is decided before
+    // the sweep is complete, which needs this task too; only the watchdog
+    // (a clock read) is checked.  A time-out set meanwhile by a workgroup
+    // that waits for this sweep is seen at the next sweep change.
+    if (sweep == w.sweep) {
+        if (a.watchdog == 0 || wall_clock64() - w.t0 <= a.watchdog) return 1;
+        int expect = ST_RUNNING;
+        __hip_atomic_compare_exchange_strong(&c->state, &expect, (int)ST_TIMEOUT, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        return 0;
+    }
+    int go = 0;
+    {
         // leaving w.sweep for good: publish it before waiting on sweep - 1
         persistent_publish(a, w);
         if (sweep > 0) {
@@ -161,6 +187,9 @@ __device__ __forceinline__ void write_back_window(const int* w, const unsigned* 
 {
     const unsigned q = (cnt + 3) >> 2;
     const int4* w4 = reinterpret_cast<const int4*>(w);
+    // four dirty labels in a row (the common case early in a solve) go out
+    // as one 16-byte store when g is 16-byte aligned
+    const bool vec = !ATOMIC && (reinterpret_cast<uintptr_t>(g) & 15) == 0;
     for (unsigned i0 = threadIdx.x; i0 < q; i0 += BLOCK * kStageUnroll) {
         unsigned bits[kStageUnroll];
         int4 val[kStageUnroll];
@@ -174,6 +203,10 @@ __device__ __forceinline__ void write_back_window(const int* w, const unsigned* 
 #pragma unroll
         for (int u = 0; u < kStageUnroll; ++u) {
             const int j = (int)(i0 + u * BLOCK) * 4;
+            if (vec && bits[u] == 15u) {
+                *reinterpret_cast<int4*>(g + j) = val[u];
+                continue;
+            }
             if (bits[u] & 1u) put<ATOMIC>(g, j, val[u].x);
             if (bits[u] & 2u) put<ATOMIC>(g, j + 1, val[u].y);
             if (bits[u] & 4u) put<ATOMIC>(g, j + 2, val[u].z);
@@ -238,9 +271,11 @@ __device__ __forceinline__ void persistent_solve(const SolveArgs& a)
 {
     __shared__ long long s_task;
     __shared__ int s_go;
-    PersistentState w{-1, 0, 0, 0};
+    PersistentState w{-1, 0, 0, 0, 0};
+    long long grp = 0, grp_end = 0;  // thread 0: the rest of its task group
     if (threadIdx.x == 0) {
-        const long long t = persistent_take(a);
+        w.t0 = a.ctl->t0;
+        const long long t = persistent_take(a, &grp, &grp_end);
         s_go = persistent_begin(a, w, t);
         s_task = t;
     }
@@ -265,7 +300,7 @@ __device__ __forceinline__ void persistent_solve(const SolveArgs& a)
         // take the next task; only a move to another sweep (or the end)
         // publishes, which needs every store of the workgroup drained and
         // the per-thread flags combined
-        if (threadIdx.x == 0) s_task = persistent_take(a);
+        if (threadIdx.x == 0) s_task = persistent_take(a, &grp, &grp_end);
         __syncthreads();
         const long long next = uniform(s_task);
         const bool leave = next < 0 || next / a.tasks != sweep;

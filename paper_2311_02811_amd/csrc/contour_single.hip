@@ -200,7 +200,11 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
 {
     Resolved r = r0;
     const bool reorder = m > 0 && wants_reorder(r0, m, n);
-    if (reorder && r.ept == 0) r.ept = 2;  // label-window tasks: most gathers hit LDS
+    if (reorder) {
+        // label windows fill the LDS of a CU: one 1024-thread workgroup each
+        if (r.block == 0) r.block = 1024;
+        if (r.ept == 0) r.ept = m >= (4LL << 20) ? 4 : 2;
+    }
     auto_geometry(d, m, &r);
     PersistentLaunch p;
     p.src_in = src;
@@ -231,6 +235,7 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
     a.tiles_per_task = 1;
     a.tasks = 0;
     a.ntiles = 0;
+    a.take = 1;
     a.win_cap = 0;
     a.win_shift = 0;
     a.win_margin = 0;
@@ -262,8 +267,13 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
         const long long resident = (long long)std::max(occ, 1) * d.cus;
         int tpt = r.chunk_tiles ? r.chunk_tiles : auto_tiles_per_task(m, tile_edges);
         if (win && !r.chunk_tiles) {
-            // a window is loaded per task: tasks of m / 1024 edges, 32 Ki to 256 Ki
-            const long long want = std::max<long long>(32768, std::min<long long>(262144, m / 1024));
+            // A window is staged per task.  Tasks of 32 Ki edges, about one
+            // source block of a sparse graph; where blocks hold many more
+            // edges than that (dense graphs), 16 Ki, so that a block's
+            // window is staged afresh, with the other workgroups' updates,
+            // several times per sweep (measured: fewer sweeps on R-MAT).
+            const long long per_block = m / std::max(1, p.ro.K);
+            const long long want = per_block > 65536 ? 16384 : 32768;
             tpt = (int)std::max<long long>(1, want / tile_edges);
         }
         // the sweep's tiles split evenly over a number of tasks that is a
@@ -275,6 +285,8 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
         a.tasks = tasks;
         a.tiles_per_task = (int)((ntiles + tasks - 1) / tasks);
         p.grid = (unsigned)std::min<long long>(g, a.tasks);
+        // each workgroup takes its share of a sweep with one atomic
+        a.take = (int)std::max<long long>(1, a.tasks / p.grid);
     }
     *out = p;
     return CONTOUR_OK;
@@ -362,6 +374,7 @@ static int run_hostloop(const DeviceInfo& d, const Resolved& r0, const int* src,
         a.tiles_per_task = 1;
         a.tasks = ntiles;
         a.ntiles = ntiles;
+        a.take = 1;
         const long long grid = r.grid ? r.grid : std::min<long long>(ntiles, (long long)d.cus * 16);
         int* other = r.sync ? ws->scratch + (reorder ? ro.elems : 0) : nullptr;
         int sweep = 0, ahead = 4;
