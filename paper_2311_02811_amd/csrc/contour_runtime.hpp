@@ -95,19 +95,13 @@ int enqueue_wg_jobs(const DeviceInfo& d, const Resolved& r, const BatchJob* d_jo
 // Edge reordering by source block (contour_reorder.hip).
 struct Reorder {
     int shift = 0;          // source block = src >> shift
-    int K = 0;              // source blocks
-    int passes = 0;         // radix passes of 5 bits
-    int G = 0;              // workgroups (chunks) of the count and scatter passes
-    long long chunk = 0;    // edges per chunk
-    int nblk = 0;           // scan blocks
+    int K = 0;              // source blocks (at most 1024)
     long long m = 0;
     long long elems = 0;    // workspace ints needed
     int* src2 = nullptr;    // workspace: reordered edges
     int* dst2 = nullptr;
-    int* tmp_src = nullptr; // workspace: intermediate pass
-    int* tmp_dst = nullptr;
-    int* counts = nullptr;  // workspace: 32 x G digit counts
-    int* sums = nullptr;    // workspace: scan block totals
+    int* hist = nullptr;    // workspace: edges per block
+    int* cursor = nullptr;  // workspace: next free slot of each block
 };
 
 // Sizes for m edges over n > 0 vertices.
