@@ -43,6 +43,13 @@ def make_workload(name: str, seed: int):
     if name == "rmat24_ef16":
         src, dst = graphgen.rmat(24, 16, seed)
         return src, dst, 1 << 24
+    if name == "rmat24_ef16_share8":
+        import numpy as np
+        # one GPU's share of the R-MAT graph under the 1-D edge split of an
+        # eight-GPU run: a seeded random eighth of the edges, all 2^24 labels
+        src, dst = graphgen.rmat(24, 16, seed)
+        keep = graphgen.share_mask(src.size, 8, 0, seed)
+        return np.ascontiguousarray(src[keep]), np.ascontiguousarray(dst[keep]), 1 << 24
     if name == "er65536_m524288":
         src, dst = graphgen.er(65536, 524288, seed)
         return src, dst, 65536
@@ -319,7 +326,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="grid4096_holes10",
-                    choices=["grid4096_holes10", "rmat24_ef16", "er65536_m524288"])
+                    choices=["grid4096_holes10", "rmat24_ef16", "er65536_m524288", "rmat24_ef16_share8"])
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--order", default="2")
     ap.add_argument("--write", default="plain", choices=["plain", "atomic"])

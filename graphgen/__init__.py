@@ -145,6 +145,12 @@ def rmat(scale: int, edge_factor: int, seed: int, a=0.57, b=0.19, c=0.19, permut
     return src, dst
 
 
+def share_mask(m: int, p: int, i: int, seed: int) -> np.ndarray:
+    """Edges of share i when m edges are split into p seeded random shares
+    (the 1-D edge split of a p-GPU run)."""
+    return np.random.default_rng([seed, 0x5EED, p]).integers(0, p, m) == i
+
+
 def shuffle_edges(src: np.ndarray, dst: np.ndarray, seed: int) -> None:
     assert src.dtype == np.int32 and dst.dtype == np.int32 and src.size == dst.size
     _load().gg_shuffle_edges(src.size, seed, _p32(src), _p32(dst))

@@ -31,6 +31,11 @@ Models
                   the asynchronous update with plain (non-atomic) stores of
                   Section III-B-3, modelled as groups of edges that all read
                   first and then store in a shuffled order, last store wins.
+  sharded_rounds  the multi-GPU design (not in the paper, one GPU is built):
+                  the edge list split into shares, each share solved with
+                  Algorithm 1's loop started from the current labels, the
+                  shares' results combined by an elementwise minimum, rounds
+                  repeated until one changes nothing.
 Operator schedules (Section III-B-4): C-1, C-2, C-m, C-11mm, C-1m1m.
 
 Loops are plain Python except in contour_sync, which uses numpy fancy indexing
@@ -247,3 +252,45 @@ def contour_lost_update(src, dst, n: int, order: int = 2, group: int = 8, seed: 
         if not active:
             return np.asarray(L, np.int32), s + 1, ok
     raise RuntimeError("no convergence within %d sweeps" % max_sweeps)
+
+
+# ------------------------------------------------- sharded (design model) --
+
+def contour_sync_from(src, dst, L0, order: int = 2, max_iter: int = 1 << 20):
+    """Algorithm 1's loop (C-Syn, MM^order) started from the labels L0 instead
+    of L[i] = i.  L0 must hold L0[x] <= x with L0[x] in x's component of the
+    graph the labels belong to.  Returns (labels, iterations)."""
+    src = np.asarray(src, np.int64)
+    dst = np.asarray(dst, np.int64)
+    L = np.asarray(L0, np.int64).copy()
+    for it in range(1, max_iter + 1):
+        Lu = sync_iteration(L, src, dst, order)
+        if np.array_equal(Lu, L):
+            return L.astype(np.int32), it
+        L = Lu
+    raise RuntimeError("no convergence within %d iterations" % max_iter)
+
+
+def sharded_rounds(src, dst, n: int, share, p: int, order: int = 2, max_rounds: int = 1 << 10,
+                   record: bool = False):
+    """The multi-GPU design on one host: edge e belongs to share share[e] in
+    [0, p); every round solves each share from the current labels
+    (contour_sync_from) and takes the elementwise minimum of the p results.
+    A round that changes nothing ends the run: the labels are then a fixed
+    point of MM on every share, hence on the whole edge list.  Returns
+    (labels, rounds, states) with states the labels after each round when
+    record is set."""
+    src = np.asarray(src, np.int64)
+    dst = np.asarray(dst, np.int64)
+    share = np.asarray(share)
+    L = np.arange(n, dtype=np.int64)
+    states = []
+    for r in range(1, max_rounds + 1):
+        parts = [contour_sync_from(src[share == i], dst[share == i], L, order)[0] for i in range(p)]
+        Ln = np.minimum.reduce([q.astype(np.int64) for q in parts]) if parts else L.copy()
+        if record:
+            states.append(Ln.astype(np.int32))
+        if np.array_equal(Ln, L):
+            return L.astype(np.int32), r, states
+        L = Ln
+    raise RuntimeError("no convergence within %d rounds" % max_rounds)

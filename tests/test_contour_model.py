@@ -206,3 +206,60 @@ def test_post_write_check_is_unsound():
             found = True
             break
     assert found
+
+
+# ------------------------------------------------ sharded rounds (design) --
+
+def _component_ids(src, dst, n):
+    return oracle.uf_labels(src, dst, n)
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 7])
+@pytest.mark.parametrize("kind", ["er", "grid", "rmat"])
+def test_sharded_rounds_reach_the_whole_graph_labels(kind, p):
+    # the combine rule of the multi-GPU design: each round solves every
+    # share from the current labels and keeps the elementwise minimum; the
+    # run must end on the labels of the whole graph, with every round's
+    # labels satisfying L[x] <= x, staying in x's component, never rising
+    if kind == "er":
+        src, dst = graphgen.er(300, 420, 3)
+        n = 300
+    elif kind == "grid":
+        src, dst = graphgen.grid_holes(16, 20, 0.3, 4)
+        n = 16 * 20
+    else:
+        src, dst = graphgen.rmat(8, 4, 5)
+        n = 1 << 8
+    share = np.random.default_rng(11 + p).integers(0, p, src.size)
+    labels, rounds, states = cm.sharded_rounds(src, dst, n, share, p, record=True)
+    exp = oracle.uf_labels(src, dst, n)
+    assert np.array_equal(labels, exp)
+    comp = _component_ids(src, dst, n)
+    prev = np.arange(n)
+    for L in states:
+        assert (L <= np.arange(n)).all()
+        assert np.array_equal(comp[L], comp)
+        assert (L <= prev).all()
+        prev = L
+    if p == 1:
+        assert rounds == 2  # one round solves, the next confirms
+    assert rounds <= 64
+
+
+def test_sharded_rounds_need_the_exchange():
+    # a path split so that no share holds two consecutive edges: one round of
+    # local solves cannot label the path, the exchange of minima must
+    src = np.arange(0, 9, dtype=np.int32)
+    dst = src + 1
+    share = (np.arange(9) % 2).astype(np.int64)
+    labels, rounds, states = cm.sharded_rounds(src, dst, 10, share, 2, record=True)
+    assert np.array_equal(labels, np.zeros(10, np.int32))
+    assert not np.array_equal(states[0], labels)
+    assert rounds > 2
+
+
+def test_sync_from_identity_equals_algorithm_1():
+    src, dst = graphgen.er(200, 300, 9)
+    a, it_a = cm.contour_sync_from(src, dst, np.arange(200), 2)
+    b, it_b, _, _ = cm.contour_sync(src, dst, 200, 2)
+    assert np.array_equal(a, b) and it_a == it_b
