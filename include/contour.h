@@ -151,6 +151,30 @@ int contour_cc_ex(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
                   int32_t* labels_inout, const contour_opts_t* opts, contour_stats_t* stats,
                   contour_stream_t stream);
 
+/* contour_cc_add_edges: labels after adding edges to a labelled graph.
+ *   src, dst      device int32[m], the new edges (ids in [0, n))
+ *   m             new edge count, >= 0, at most (2^31 - 4) / 3
+ *   labels_inout  device int32[n]: on entry the exact labels of some graph G on
+ *                 the same n vertices (as returned by contour_cc / contour_cc_ex,
+ *                 each vertex labelled with its component's minimum id); on
+ *                 return the labels of G plus the new edges
+ *   opts          NULL for defaults; warm_start is implied
+ *   stats         as for contour_cc_ex
+ * Not in the paper; it uses the property that any state with L[x] <= x and
+ * L[x] in x's component is a valid start (Algorithm 1 only ever lowers labels
+ * within a component, Section II-A).  Only the new edges are swept, each with
+ * two ties (w, L[w]) and (v, L[v]) to the old roots of its endpoints, from the
+ * old labels; every label is then replaced by the root of its chain.  The old
+ * edges are never read, so the cost is O(m) per sweep plus O(n) for the final
+ * pass.  Labels on entry that break 0 <= L[x] <= x are refused as for a warm
+ * start of contour_cc_ex (stats status CONTOUR_EINVAL, labels unchanged); labels
+ * that satisfy it but are not the exact labels of a graph give labels of some
+ * coarser state, not an error.  A workspace of 6 m ints is kept per (device,
+ * stream) and reused.  Returns as contour_cc_ex. */
+int contour_cc_add_edges(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
+                         int32_t* labels_inout, const contour_opts_t* opts, contour_stats_t* stats,
+                         contour_stream_t stream);
+
 /* ------------------------------------------------------------ batches -- */
 /* A CSR-of-graphs batch of G independent graphs.  Graph g owns local vertex
  * ids 0..n_g-1 with n_g = vertex_offsets[g+1] - vertex_offsets[g] (< 2^31),

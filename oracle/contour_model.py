@@ -294,3 +294,34 @@ def sharded_rounds(src, dst, n: int, share, p: int, order: int = 2, max_rounds: 
             return L.astype(np.int32), r, states
         L = Ln
     raise RuntimeError("no convergence within %d rounds" % max_rounds)
+
+
+# ------------------------------------------------- incremental (new edges) --
+
+def flatten(L) -> np.ndarray:
+    """Every label replaced by the root of its chain (L[x], L[L[x]], ... until
+    a fixed point); chains strictly decrease, so this ends."""
+    L = np.asarray(L, np.int64).copy()
+    while True:
+        Ln = L[L]
+        if np.array_equal(Ln, L):
+            return L.astype(np.int32)
+        L = Ln
+
+
+def add_edges(labels, src, dst, order: int = 2) -> np.ndarray:
+    """Labels of G plus the edges (src, dst), given `labels` = the exact
+    labels of G (every vertex points at its component's minimum, the old
+    root).  The sweeps run, from the old labels (Algorithm 1's loop with a
+    warm start), over the new edges plus a tie (x, old root of x) for each
+    endpoint x of a new edge; every label is then replaced by the root of its
+    chain.  The ties keep an endpoint connected to its old component after
+    its own label has been lowered: without them the old edges that made it
+    part of that component would have to be swept again."""
+    labels = np.asarray(labels, np.int64)
+    src = np.asarray(src, np.int64)
+    dst = np.asarray(dst, np.int64)
+    s = np.concatenate([src, src, dst])
+    d = np.concatenate([dst, labels[src], labels[dst]])
+    L, _ = contour_sync_from(s, d, labels, order)
+    return flatten(L)

@@ -128,6 +128,56 @@ def cc_ex(src, dst, n: int, labels=None, stream=None, stats: bool = True, **opts
     return labels, st
 
 
+def add_edges(src, dst, n: int, labels, stream=None, stats: bool = True, **opts):
+    """contour_cc_add_edges: `labels` (int32 CUDA tensor of n) holds the exact
+    labels of a graph; after the call (stream ordered) it holds the labels of
+    that graph plus the edges (src, dst).  Returns (labels, stats_tensor)."""
+    torch = _torch()
+    _check_edges(src, dst)
+    if labels.dtype != torch.int32 or not labels.is_cuda or labels.numel() != n:
+        raise ValueError("labels must be an int32 CUDA tensor of n elements")
+    o = make_opts(**opts)
+    st = torch.zeros(4, dtype=torch.int32, device=labels.device) if stats else None
+    rc = load().contour_cc_add_edges(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                     src.numel(), int(n), ctypes.c_void_p(labels.data_ptr()),
+                                     ctypes.byref(o), ctypes.c_void_p(st.data_ptr() if stats else 0),
+                                     _stream_ptr(stream))
+    if rc != OK:
+        raise ContourError(rc, "contour_cc_add_edges")
+    return labels, st
+
+
+class Graph:
+    """A graph on n vertices whose connected components are kept current on
+    the device as edges arrive (a front end over contour_cc_add_edges).
+
+        g = Graph(n)
+        g.add_edges(src, dst)        # int32 CUDA tensors
+        g.labels                     # labels[v] = minimum id of v's component
+        g.num_components(), g.connected(u, v)
+    """
+
+    def __init__(self, n: int, device="cuda", **opts):
+        torch = _torch()
+        self.n = int(n)
+        self.opts = opts
+        self.labels = torch.arange(self.n, dtype=torch.int32, device=device)
+        self.num_edges = 0
+
+    def add_edges(self, src, dst, stream=None):
+        _, st = add_edges(src, dst, self.n, self.labels, stream=stream, **self.opts)
+        self.num_edges += src.numel()
+        return read_stats(st)
+
+    def num_components(self) -> int:
+        torch = _torch()
+        ids = torch.arange(self.n, dtype=torch.int32, device=self.labels.device)
+        return int((self.labels == ids).sum().item())
+
+    def connected(self, u: int, v: int) -> bool:
+        return bool(self.labels[int(u)].item() == self.labels[int(v)].item())
+
+
 def read_stats(st) -> Stats:
     v = st.tolist()
     return Stats(v[0], v[1], v[2])

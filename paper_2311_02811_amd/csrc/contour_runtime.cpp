@@ -103,6 +103,20 @@ int workspace_scratch(Workspace* ws, hipStream_t stream, long long elems)
     return CONTOUR_OK;
 }
 
+int workspace_aux(Workspace* ws, hipStream_t stream, long long elems)
+{
+    if (ws->aux_elems >= elems) return CONTOUR_OK;
+    CONTOUR_HIP(hipStreamSynchronize(stream));
+    if (ws->aux) {
+        CONTOUR_HIP(hipFree(ws->aux));
+        ws->aux = nullptr;
+        ws->aux_elems = 0;
+    }
+    CONTOUR_HIP(hipMalloc((void**)&ws->aux, sizeof(int) * (size_t)elems));
+    ws->aux_elems = elems;
+    return CONTOUR_OK;
+}
+
 int resolve_opts(const contour_opts_t* o, Resolved* r)
 {
     contour_opts_t d;

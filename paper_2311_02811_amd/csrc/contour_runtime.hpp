@@ -39,6 +39,8 @@ struct Workspace {
     Ctl* host_ctl = nullptr;  // host pinned
     int* scratch = nullptr;   // device, `scratch_elems` ints
     long long scratch_elems = 0;
+    int* aux = nullptr;       // device, `aux_elems` ints: a second grow-only array
+    long long aux_elems = 0;
 };
 
 // Look up (or create) the workspace of the current device and `stream`.
@@ -48,6 +50,8 @@ int workspace_for(hipStream_t stream, Workspace** out);
 // Make ws->scratch hold at least `elems` ints (may free and reallocate; the
 // caller's stream is synchronised first when it grows).
 int workspace_scratch(Workspace* ws, hipStream_t stream, long long elems);
+// The same for ws->aux (inputs a call builds before its solve uses scratch).
+int workspace_aux(Workspace* ws, hipStream_t stream, long long elems);
 
 // Resolved options for a single solve.
 struct Resolved {

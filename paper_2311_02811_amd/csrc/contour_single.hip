@@ -114,6 +114,45 @@ __global__ void k_copy_labels(const int* R, int* W, unsigned n, const Ctl* c)
     for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) W[i] = R[i];
 }
 
+// Edges added to a labelled graph: edge i of the new list becomes three
+// edges of the augmented list, (w, v), (w, L[w]) and (v, L[v]), where L holds
+// the graph's exact labels (every vertex points at its component's minimum,
+// its old root).  The two ties keep an endpoint joined to its old component
+// after the sweeps lower its own label, so the old edges never need another
+// sweep.  An id outside [0, n) is copied unchanged (no label read) and the
+// sweep's range check reports it.
+__global__ void k_tie_edges(const int* __restrict__ src, const int* __restrict__ dst, long long m,
+                            const int* __restrict__ L, unsigned n, int* __restrict__ as, int* __restrict__ ad)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < m; i += (long long)gridDim.x * blockDim.x) {
+        const int w = src[i], v = dst[i];
+        as[i] = w;
+        ad[i] = v;
+        as[m + i] = w;
+        ad[m + i] = (unsigned)w < n ? L[w] : w;
+        as[2 * m + i] = v;
+        ad[2 * m + i] = (unsigned)v < n ? L[v] : v;
+    }
+}
+
+// Every label replaced by the root of its chain (L[x], L[L[x]], ... until
+// L[r] = r).  Chains strictly decrease, so the walk ends; concurrent walks
+// only replace a label by another vertex of the same chain.  Skipped when
+// the warm start was refused (the labels are then left as they were).
+__global__ void k_flatten(int* L, unsigned n, const Ctl* c)
+{
+    if (c->state == ST_BAD_START) return;
+    for (unsigned x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
+        unsigned r = (unsigned)L[x];
+        for (;;) {
+            const unsigned q = (unsigned)L[r];
+            if (q >= r) break;
+            r = q;
+        }
+        L[x] = (int)r;
+    }
+}
+
 // ----------------------------------------------------- dispatch ---------
 
 typedef void (*persistent_fn)(SolveArgs);
@@ -469,6 +508,53 @@ int contour_cc(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int
                contour_stream_t stream)
 {
     return contour_cc_ex(src, dst, m, n, labels_out, nullptr, nullptr, stream);
+}
+
+int contour_cc_add_edges(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int32_t* labels_inout,
+                         const contour_opts_t* opts, contour_stats_t* stats, contour_stream_t stream)
+{
+    if (m < 0 || n < 0) return CONTOUR_EINVAL;
+    if (n > 0 && !labels_inout) return CONTOUR_EINVAL;
+    if (m > 0 && (!src || !dst)) return CONTOUR_EINVAL;
+    if (m > (0x7fffffffLL - 3) / 3) return CONTOUR_EINVAL;  // the augmented list has 3m edges
+    contour::Resolved r;
+    int rc = contour::resolve_opts(opts, &r);
+    if (rc) return rc;
+    r.warm = true;
+    if (n == 0) return contour_cc_ex(src, dst, m, n, labels_inout, opts, stats, stream);
+    hipStream_t s = (hipStream_t)stream;
+    contour::Workspace* ws = nullptr;
+    rc = contour::workspace_for(s, &ws);
+    if (rc) return rc;
+    const long long mp = (m + 3) & ~3LL;
+    int* as = nullptr;
+    int* ad = nullptr;
+    if (m > 0) {
+        // both arrays start on 16-byte boundaries
+        rc = contour::workspace_aux(ws, s, 6 * mp);
+        if (rc) return rc;
+        as = ws->aux;
+        ad = ws->aux + 3 * mp;
+        contour::DeviceInfo d;
+        rc = contour::device_info(&d);
+        if (rc) return rc;
+        const unsigned blocks = (unsigned)std::max<long long>(
+            1, std::min<long long>((m + 255) / 256, (long long)d.cus * 8));
+        hipLaunchKernelGGL(contour::k_tie_edges, dim3(blocks), dim3(256), 0, s, src, dst, (long long)m,
+                           (const int*)labels_inout, (unsigned)n, as, ad);
+        CONTOUR_HIP(hipGetLastError());
+    }
+    rc = contour::run_solve(as, ad, 3 * (long long)m, n, labels_inout, r, stats, s);
+    if (rc) return rc;
+    contour::DeviceInfo d;
+    rc = contour::device_info(&d);
+    if (rc) return rc;
+    const unsigned blocks = (unsigned)std::max<long long>(
+        1, std::min<long long>(((long long)n + 255) / 256, (long long)d.cus * 8));
+    hipLaunchKernelGGL(contour::k_flatten, dim3(blocks), dim3(256), 0, s, labels_inout, (unsigned)n,
+                       (const contour::Ctl*)ws->ctl);
+    CONTOUR_HIP(hipGetLastError());
+    return CONTOUR_OK;
 }
 
 }  // extern "C"

@@ -66,3 +66,17 @@ def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         L.load()
+
+
+def test_add_edges_argument_errors_without_touching_the_device():
+    import paper_2311_02811_amd as contour
+    lib = contour.load()
+    assert lib.contour_cc_add_edges(None, None, -1, 4, None, None, None, None) == contour.EINVAL
+    assert lib.contour_cc_add_edges(None, None, 3, 4, None, None, None, None) == contour.EINVAL
+    assert lib.contour_cc_add_edges(None, None, 0, 4, None, None, None, None) == contour.EINVAL
+    # the augmented list has 3m edges, which must fit int32 slots
+    assert lib.contour_cc_add_edges(ctypes.c_void_p(16), ctypes.c_void_p(16), 1 << 30, 4,
+                                    ctypes.c_void_p(16), None, None, None) == contour.EINVAL
+    o = contour.make_opts()
+    o.order = 0x7fff
+    assert lib.contour_cc_add_edges(None, None, 0, 0, None, ctypes.byref(o), None, None) == contour.EINVAL

@@ -263,3 +263,54 @@ def test_sync_from_identity_equals_algorithm_1():
     a, it_a = cm.contour_sync_from(src, dst, np.arange(200), 2)
     b, it_b, _, _ = cm.contour_sync(src, dst, 200, 2)
     assert np.array_equal(a, b) and it_a == it_b
+
+
+# ------------------------------------------------ incremental new edges --
+
+@pytest.mark.parametrize("order", [1, 2, 3, cm.FULL])
+@pytest.mark.parametrize("seed", range(12))
+def test_add_edges_in_batches_reaches_whole_graph_labels(seed, order):
+    # edges arrive in batches; after each batch only the new edges are swept
+    # from the previous labels, then chains are flattened: the labels must be
+    # those of every edge so far (the union-find oracle on the union)
+    rng = np.random.default_rng(seed)
+    kind = seed % 3
+    if kind == 0:
+        src, dst = graphgen.er(400, 500, seed)
+        n = 400
+    elif kind == 1:
+        src, dst = graphgen.grid_holes(15, 25, 0.2, seed)
+        n = 15 * 25
+    else:
+        src, dst = graphgen.rmat(8, 3, seed)
+        n = 256
+    cuts = np.sort(rng.integers(0, src.size + 1, 5))
+    bounds = [0, *cuts.tolist(), src.size]
+    L = np.arange(n, dtype=np.int32)
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        L = cm.add_edges(L, src[a:b], dst[a:b], order)
+        assert np.array_equal(L, oracle.uf_labels(src[:b], dst[:b], n))
+
+
+def test_add_edges_needs_the_ties_to_old_roots():
+    # Sweeping the new edges alone from the old labels is not enough: an
+    # endpoint whose label is lowered stops pointing at its old root, and the
+    # old edges that tie it to its component are not swept again.  With the
+    # ties (x, old root of x) the whole-graph labels come out every time.
+    src, dst = graphgen.er(400, 500, 0)
+    old = oracle.uf_labels(src[:154], dst[:154], 400)
+    bare = cm.flatten(cm.contour_sync_from(src[154:256], dst[154:256], old, 2)[0])
+    assert not np.array_equal(bare, oracle.uf_labels(src[:256], dst[:256], 400))
+    assert np.array_equal(cm.add_edges(old, src[154:256], dst[154:256], 2),
+                          oracle.uf_labels(src[:256], dst[:256], 400))
+    rng = np.random.default_rng(3)
+    for trial in range(200):
+        n = 12
+        src, dst = graphgen.er(n, 8, trial)
+        k = int(rng.integers(0, src.size + 1))
+        L = cm.add_edges(oracle.uf_labels(src[:k], dst[:k], n), src[k:], dst[k:], 2)
+        assert np.array_equal(L, oracle.uf_labels(src, dst, n)), trial
+
+
+def test_flatten_of_a_chain():
+    assert np.array_equal(cm.flatten([0, 0, 1, 2, 3, 5]), [0, 0, 0, 0, 0, 5])
