@@ -93,6 +93,21 @@ __device__ __forceinline__ void put(int* L, int x, int z)
         L[x] = z;
 }
 
+// Atomic minimum of z into L[x] from the active lanes of a wave, where many
+// lanes often target the same label with the same value (a component's root
+// late in a solve): lanes equal in both to the first active lane leave the
+// atomic to that lane.  Exact: the minimum is the same, with fewer atomics on
+// one address.
+__device__ __forceinline__ void put_min_shared(int* L, int x, int z)
+{
+    const int x0 = __builtin_amdgcn_readfirstlane(x);
+    const int z0 = __builtin_amdgcn_readfirstlane(z);
+    const unsigned long long active = __builtin_amdgcn_ballot_w64(true);
+    const bool leader = (int)__lane_id() == __builtin_ctzll(active);
+    if (leader || x != x0 || z != z0)
+        __hip_atomic_fetch_min(L + x, z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------------------
 // Edge tile: BLOCK * EPT consecutive edges starting at `base`, EPT per
 // thread, read so that every load instruction of a wave covers contiguous
@@ -458,7 +473,7 @@ struct WindowLabels {
                 lds[i] = z;
             atomicOr(&dirty[i >> 5], 1u << (i & 31));
         } else {
-            put<ATOMIC>(G, x, z);
+            put_min_shared(G, x, z);  // global memory: atomic minimum (see persistent_solve)
         }
     }
 };

@@ -177,19 +177,23 @@ __device__ __forceinline__ void stage_window(int* w, const int* g, unsigned cnt)
     }
 }
 
-// Write the labels of window w whose dirty bit is set back to g (plain or
-// atomic-minimum stores, as the write mode says).  Each thread handles four
-// consecutive labels per step (one 16-byte LDS read; the window's LDS holds a
-// multiple of 32 labels, so the read stays inside it) and kStageUnroll steps
-// at a time.
+// Write the labels of window w whose dirty bit is set back to global memory
+// (g = labels + lo, buffer resource rsrc over the labels, byte offset of g
+// in it goff).  Plain mode writes through to memory (sc1 stores: 16 bytes for
+// four dirty labels in a row, else 4 bytes each), atomic mode takes the
+// atomic minimum of every dirty label (see persistent_solve).  Each thread
+// handles four consecutive labels per step (one 16-byte LDS read; the
+// window's LDS holds a multiple of 32 labels, so the read stays inside it)
+// and kStageUnroll steps at a time.
+constexpr int kStoreWriteThrough = 16;  // buffer cache policy: sc1
+
 template <int BLOCK, bool ATOMIC>
-__device__ __forceinline__ void write_back_window(const int* w, const unsigned* dirty, int* g, unsigned cnt)
+__device__ __forceinline__ void write_back_window(const int* w, const unsigned* dirty, int* g,
+                                                  __amdgpu_buffer_rsrc_t rsrc, unsigned goff, unsigned cnt)
 {
+    typedef int v4i __attribute__((ext_vector_type(4)));
     const unsigned q = (cnt + 3) >> 2;
     const int4* w4 = reinterpret_cast<const int4*>(w);
-    // four dirty labels in a row (the common case early in a solve) go out
-    // as one 16-byte store when g is 16-byte aligned
-    const bool vec = !ATOMIC && (reinterpret_cast<uintptr_t>(g) & 15) == 0;
     for (unsigned i0 = threadIdx.x; i0 < q; i0 += BLOCK * kStageUnroll) {
         unsigned bits[kStageUnroll];
         int4 val[kStageUnroll];
@@ -202,15 +206,21 @@ __device__ __forceinline__ void write_back_window(const int* w, const unsigned* 
         }
 #pragma unroll
         for (int u = 0; u < kStageUnroll; ++u) {
-            const int j = (int)(i0 + u * BLOCK) * 4;
-            if (vec && bits[u] == 15u) {
-                *reinterpret_cast<int4*>(g + j) = val[u];
-                continue;
+            const unsigned j = (i0 + u * BLOCK) * 4;
+            if (ATOMIC) {
+                if (bits[u] & 1u) put<true>(g, (int)j, val[u].x);
+                if (bits[u] & 2u) put<true>(g, (int)j + 1, val[u].y);
+                if (bits[u] & 4u) put<true>(g, (int)j + 2, val[u].z);
+                if (bits[u] & 8u) put<true>(g, (int)j + 3, val[u].w);
+            } else if (bits[u] == 15u) {
+                const v4i v = {val[u].x, val[u].y, val[u].z, val[u].w};
+                __builtin_amdgcn_raw_buffer_store_b128(v, rsrc, goff + j * 4, 0, kStoreWriteThrough);
+            } else {
+                if (bits[u] & 1u) __builtin_amdgcn_raw_buffer_store_b32(val[u].x, rsrc, goff + j * 4, 0, kStoreWriteThrough);
+                if (bits[u] & 2u) __builtin_amdgcn_raw_buffer_store_b32(val[u].y, rsrc, goff + j * 4 + 4, 0, kStoreWriteThrough);
+                if (bits[u] & 4u) __builtin_amdgcn_raw_buffer_store_b32(val[u].z, rsrc, goff + j * 4 + 8, 0, kStoreWriteThrough);
+                if (bits[u] & 8u) __builtin_amdgcn_raw_buffer_store_b32(val[u].w, rsrc, goff + j * 4 + 12, 0, kStoreWriteThrough);
             }
-            if (bits[u] & 1u) put<ATOMIC>(g, j, val[u].x);
-            if (bits[u] & 2u) put<ATOMIC>(g, j + 1, val[u].y);
-            if (bits[u] & 4u) put<ATOMIC>(g, j + 2, val[u].z);
-            if (bits[u] & 8u) put<ATOMIC>(g, j + 3, val[u].w);
         }
     }
 }
@@ -254,10 +264,24 @@ __device__ __forceinline__ bool window_task(const SolveArgs& a, long long first_
     const bool pred = run_tiles_lab<EPT, BLOCK, ATOMIC, WindowLabels, 1>(
         a.src, a.dst, lab, first_tile, count, 1, a.m, a.n, order, rerr);
     __syncthreads();
-    write_back_window<BLOCK, ATOMIC>(wl, dirty, a.L + lo, cnt);
+    write_back_window<BLOCK, ATOMIC>(wl, dirty, a.L + lo, lab.rsrc, lo * 4u, cnt);
     return pred;
 }
 
+// Label stores into global memory are coherent across the XCDs in every
+// write mode: atomic minima, or (window write-back in plain mode) stores
+// written through to memory.  The early convergence check needs every read
+// of the last sweep to see the labels' final values.  With ordinary cached
+// stores, workgroups on different XCDs racing on one cache line (the lost
+// updates of the asynchronous update) could leave an XCD holding, in its own
+// L2, a line it wrote itself with a smaller label than memory ended up with;
+// the sweep-boundary release/acquire (agent or system scope) did not refresh
+// it, and a sweep then passed as unchanged over an edge whose endpoints
+// differ (observed on the MI355X in batched solves: a few vertices of 1 to 3
+// of 916 graphs, in some launches; none with the coherent stores).  Stores
+// into a label window in LDS, which one workgroup owns, follow the write
+// mode (plain or atomic minimum).
+//
 // The task loop.  Its thread-0 sections (take a task; begin it, which may
 // spin) each end at a barrier, and all loop control is read back from LDS
 // through readfirstlane, so every lane of a wave passes the same barriers in
@@ -269,7 +293,12 @@ __device__ __forceinline__ bool window_task(const SolveArgs& a, long long first_
 template <int EPT, int BLOCK, bool ATOMIC, bool WIN = false>
 __device__ __forceinline__ void persistent_solve(const SolveArgs& a)
 {
-    __shared__ long long s_task;
+    // s_task is read by every wave at the top of an iteration and rewritten
+    // by thread 0 only after the next barrier; the next task goes through
+    // s_next, because without a barrier inside a task (no label window) a
+    // fast wave 0 would otherwise overwrite s_task before a slow wave has
+    // read it, and that wave would work on the wrong task.
+    __shared__ long long s_task, s_next;
     __shared__ int s_go;
     PersistentState w{-1, 0, 0, 0, 0};
     long long grp = 0, grp_end = 0;  // thread 0: the rest of its task group
@@ -294,15 +323,15 @@ __device__ __forceinline__ void persistent_solve(const SolveArgs& a)
         if (WIN)
             pred = window_task<EPT, BLOCK, ATOMIC>(a, first, count, order, rerr);
         else
-            pred = run_tiles_order<EPT, BLOCK, ATOMIC>(a.src, a.dst, a.L, a.L, first, count, 1, a.m, a.n, order,
-                                                       rerr);
+            pred = run_tiles_order<EPT, BLOCK, true>(a.src, a.dst, a.L, a.L, first, count, 1, a.m, a.n, order,
+                                                     rerr);
         changed |= pred ? 1 : 0;
         // take the next task; only a move to another sweep (or the end)
         // publishes, which needs every store of the workgroup drained and
         // the per-thread flags combined
-        if (threadIdx.x == 0) s_task = persistent_take(a, &grp, &grp_end);
+        if (threadIdx.x == 0) s_next = persistent_take(a, &grp, &grp_end);
         __syncthreads();
-        const long long next = uniform(s_task);
+        const long long next = uniform(s_next);
         const bool leave = next < 0 || next / a.tasks != sweep;
         int any = 0, anyerr = 0;
         if (leave) {
@@ -317,6 +346,7 @@ __device__ __forceinline__ void persistent_solve(const SolveArgs& a)
             w.changed |= any;
             w.err |= anyerr;
             s_go = persistent_begin(a, w, next);
+            s_task = next;
         }
         __syncthreads();
     }

@@ -172,3 +172,42 @@ def test_batched_config_full(contour):
     assert np.all(st[:, 0] == 0)
     print("batch sweeps: max %d mean %.2f" % (st[:, 1].max(), st[:, 1].mean()))
     plan.close()
+
+
+@pytest.mark.parametrize("spec", [
+    [dict(order=2), dict(order=2), dict(order="full", block=512, edges_per_thread=4)],
+    [dict(order=2), dict(order=2), dict(order=2, block=512, edges_per_thread=4)],
+    [dict(order=2), dict(order=2), dict(order=2, block=256, edges_per_thread=8)],
+], ids=["full-512x4", "2-512x4", "2-256x8"])
+def test_batched_many_multi_workgroup_graphs_repeated(contour, spec):
+    # ~900 graphs solved by several workgroups each (class 2), with
+    # workgroups moving between graphs, checked on every one of several
+    # launches.  A regression test of a race on the persistent loop's task
+    # word when a task has no barrier inside (no label window): a slow wave
+    # could read the next task instead of the current one, skip edges, and
+    # let a sweep pass as unchanged too early.
+    banner("generating the 20,000-graph batch")
+    b = graphgen.batch(20000, 1)
+    exp = oracle.uf_batch(b.edge_off, b.vertex_off, b.src, b.dst)
+    s, d = dev(b.src), dev(b.dst)
+    plan = contour.BatchPlan(b.edge_off, b.vertex_off, s, d,
+                             tuning=contour.make_tuning(spec, 0, 65536))
+    banner("classes %r" % plan.classes())
+    assert plan.classes()[2] > 500
+    for rep in range(4):
+        plan.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(plan.labels.cpu().numpy(), exp), rep
+    plan.close()
+
+
+def test_single_graph_persistent_without_window_repeated(contour):
+    # the same loop on one graph, no reordering (tasks without barriers)
+    src, dst = graphgen.er(200000, 1600000, 17)
+    s, d = dev(src), dev(dst)
+    exp = oracle.uf_labels(src, dst, 200000)
+    for geo in (dict(block=512, edges_per_thread=4), dict(block=1024, edges_per_thread=4),
+                dict(block=256, edges_per_thread=8)):
+        for rep in range(10):
+            labels, st = contour.cc_ex(s, d, 200000, reorder="off", **geo)
+            assert np.array_equal(labels.cpu().numpy(), exp), (geo, rep)
