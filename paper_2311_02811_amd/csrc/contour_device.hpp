@@ -443,6 +443,19 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t label_buffer(const int* G, uns
                                              (int)kBufferDataFormat32);
 }
 
+// Stores outside the window go to a small hash table in LDS (kHubSlots
+// entries of id and minimum value), flushed to global memory with one
+// atomic minimum per entry at the end of the task: late in a solve most of
+// them hook the same few component roots, which would otherwise take an
+// atomic in memory per edge.  An id whose slot is held by another id takes
+// the global atomic directly.
+constexpr int kHubSlots = 1024;
+
+__device__ __forceinline__ unsigned hub_slot(int x)
+{
+    return ((unsigned)x * 2654435761u) >> (32 - 10);  // kHubSlots = 2^10
+}
+
 struct WindowLabels {
     int* lds;
     unsigned* dirty;
@@ -451,6 +464,8 @@ struct WindowLabels {
     int* G;
     __amdgpu_buffer_rsrc_t rsrc;
     unsigned oob;  // a byte offset past the end of G: 4 n
+    int* hkey;     // LDS hub table: ids (-1: free) ...
+    int* hval;     // ... and the smallest value stored to each
     __device__ __forceinline__ int ld(int x) const
     {
         typedef __attribute__((address_space(3))) const int* lds_ptr;
@@ -473,7 +488,12 @@ struct WindowLabels {
                 lds[i] = z;
             atomicOr(&dirty[i >> 5], 1u << (i & 31));
         } else {
-            put_min_shared(G, x, z);  // global memory: atomic minimum (see persistent_solve)
+            const unsigned h = hub_slot(x);
+            const int k = atomicCAS(&hkey[h], -1, x);
+            if (k == -1 || k == x)
+                atomicMin(&hval[h], z);
+            else
+                put_min_shared(G, x, z);  // global memory: atomic minimum (see persistent_solve)
         }
     }
 };

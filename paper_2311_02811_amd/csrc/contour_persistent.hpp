@@ -257,13 +257,23 @@ __device__ __forceinline__ bool window_task(const SolveArgs& a, long long first_
     const unsigned cnt = uniform((int)s_cnt);
     int* wl = dyn_lds;
     unsigned* dirty = reinterpret_cast<unsigned*>(dyn_lds + a.win_cap);
+    int* hkey = dyn_lds + a.win_cap + a.win_cap / 32;
+    int* hval = hkey + kHubSlots;
     stage_window<BLOCK>(wl, a.L + lo, cnt);
     for (unsigned i = threadIdx.x; i < (cnt + 31) / 32; i += BLOCK) dirty[i] = 0;
+    for (unsigned i = threadIdx.x; i < (unsigned)kHubSlots; i += BLOCK) {
+        hkey[i] = -1;
+        hval[i] = 0x7fffffff;
+    }
     __syncthreads();
-    const WindowLabels lab{wl, dirty, lo, cnt, a.L, label_buffer(a.L, a.n), a.n * 4u};
+    const WindowLabels lab{wl, dirty, lo, cnt, a.L, label_buffer(a.L, a.n), a.n * 4u, hkey, hval};
     const bool pred = run_tiles_lab<EPT, BLOCK, ATOMIC, WindowLabels, 1>(
         a.src, a.dst, lab, first_tile, count, 1, a.m, a.n, order, rerr);
     __syncthreads();
+    for (unsigned i = threadIdx.x; i < (unsigned)kHubSlots; i += BLOCK) {
+        const int k = hkey[i];
+        if (k >= 0) __hip_atomic_fetch_min(a.L + k, hval[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     write_back_window<BLOCK, ATOMIC>(wl, dirty, a.L + lo, lab.rsrc, lo * 4u, cnt);
     return pred;
 }
