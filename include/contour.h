@@ -77,7 +77,14 @@ typedef enum {
 #define CONTOUR_SCHED_1M1M 2  /* order 1 and `order` alternately, from 1 (C-1m1m) */
 
 /* Write rule of the conditional assignment. */
-#define CONTOUR_WRITE_PLAIN 0  /* if (read > z) L[x] = z;  benign race, Section III-B-3 */
+/* CONTOUR_WRITE_PLAIN: if (read > z) L[x] = z, a benign race (Section III-B-3),
+ * where memory is coherent: in LDS label windows, between the kernels of the
+ * host-loop driver, and for one-workgroup batched graphs.  Inside the
+ * persistent kernels the XCDs' L2 caches are not coherent for cached stores,
+ * so stores into global memory there are written through or atomic minima
+ * in either mode; the labels are the same, the early convergence check stays
+ * sound. */
+#define CONTOUR_WRITE_PLAIN 0
 #define CONTOUR_WRITE_ATOMIC 1 /* if (read > z) atomic_min(&L[x], z);  Eq. (cas) */
 
 /* Update rule. */
