@@ -158,6 +158,25 @@ int contour_cc_ex(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
                   int32_t* labels_inout, const contour_opts_t* opts, contour_stats_t* stats,
                   contour_stream_t stream);
 
+/* contour_group_edges: the edge list grouped by source block, as a solve that
+ * reorders prepares it before its first sweep (the asynchronous update of
+ * Algorithm 1 may take the edges in any order, Section III-B-1).
+ *   src, dst          device int32[m], the edges
+ *   m                 edge count, 0 <= m < 2^31 - 1 (0: nothing is done)
+ *   n                 vertex count, > 0
+ *   src_out, dst_out  device int32[m], written; must not overlap src or dst
+ * The output holds the same (src, dst) pairs, unchanged.  They are ordered by
+ * block b = min(src >> s, K - 1), src read as unsigned, where s is the
+ * smallest shift with (n - 1) >> s < 1024 and K = ((n - 1) >> s) + 1 (so an
+ * id outside [0, n) lands in block K - 1).  Within a block they follow the
+ * chunks of 8192 consecutive input edges in input order; within one
+ * (block, chunk) run the order is unspecified.  A workspace of about m / 8
+ * ints is kept per (device, stream) and reused.  Returns CONTOUR_OK,
+ * CONTOUR_EINVAL (negative or too large m, n <= 0, a NULL array with m > 0),
+ * CONTOUR_ENOMEM or CONTOUR_EHIP. */
+int contour_group_edges(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
+                        int32_t* src_out, int32_t* dst_out, contour_stream_t stream);
+
 /* contour_cc_add_edges: labels after adding edges to a labelled graph.
  *   src, dst      device int32[m], the new edges (ids in [0, n))
  *   m             new edge count, >= 0, at most (2^31 - 4) / 3

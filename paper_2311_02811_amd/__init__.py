@@ -128,6 +128,20 @@ def cc_ex(src, dst, n: int, labels=None, stream=None, stats: bool = True, **opts
     return labels, st
 
 
+def group_edges(src, dst, n: int, stream=None):
+    """contour_group_edges: (src_out, dst_out), the edge list grouped by source
+    block as a reordering solve prepares it (stream ordered)."""
+    torch = _torch()
+    _check_edges(src, dst)
+    so, do = torch.empty_like(src), torch.empty_like(dst)
+    rc = load().contour_group_edges(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                    src.numel(), int(n), ctypes.c_void_p(so.data_ptr()),
+                                    ctypes.c_void_p(do.data_ptr()), _stream_ptr(stream))
+    if rc != OK:
+        raise ContourError(rc, "contour_group_edges")
+    return so, do
+
+
 def add_edges(src, dst, n: int, labels, stream=None, stats: bool = True, **opts):
     """contour_cc_add_edges: `labels` (int32 CUDA tensor of n) holds the exact
     labels of a graph; after the call (stream ordered) it holds the labels of

@@ -6,19 +6,28 @@
 // the copy then gather labels from a narrow id range, which the sweep stages
 // in LDS.  The order of the edges inside a block is left free.
 //
-// One counting pass and one scatter pass:
-//   count    a histogram of the blocks (per-workgroup LDS histograms, then
-//            one global atomic add per block and workgroup);
-//   scan     one workgroup turns it into the first slot of every block and
-//            sets each block's cursor there;
-//   scatter  a workgroup loads 16 Ki edges, ranks them by block in LDS
-//            (LDS atomics), reserves each block's run of slots with one
-//            global atomic add on the block's cursor, places the edges in
-//            block order in LDS and writes them out with consecutive lanes
-//            on consecutive slots, so each block's run (16 edges on average
-//            for 1024 blocks) is stored as contiguous words.
-// An id outside [0, n) goes to the last block unchanged; the sweep's own
-// range check rejects it.
+// The edge list is cut into chunks of 8 Ki edges; the grouped copy holds,
+// for every block, the chunks' edges of that block in chunk order:
+//   count    per chunk, a histogram of the blocks (LDS), written as one row
+//            of the chunk x block count matrix; per group of 128 chunks, the
+//            sums of those rows (global atomic adds, no return value);
+//   scan     one workgroup: the first slot of every block, and from it the
+//            first slot of every (chunk group, block) run;
+//   offsets  per chunk group, the first slot of every (chunk, block) run,
+//            written over the count matrix;
+//   scatter  a workgroup loads one chunk, ranks its edges by block in LDS
+//            (LDS atomics), places them in block order in LDS and writes
+//            them out with consecutive lanes on consecutive slots (8 edges
+//            per block on average for 1024 blocks).  Each XCD takes one
+//            eighth of the chunks in order, so the runs of neighbouring
+//            chunks, which lie next to each other in the copy, are written
+//            through one L2 at about the same time and leave it as whole
+//            lines.  A workgroup holds 64 KiB of LDS, so two share a CU and
+//            one's loads overlap the other's ranking and writes.
+// Every slot is known before the scatter: no workgroup waits on a global
+// atomic with a return value, and each block lists its edges chunk by chunk
+// in input order, which on power-law graphs also saves sweeps (the edges of
+// a block keep the input's locality).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,11 +38,15 @@ namespace contour {
 
 static constexpr int kMaxBuckets = 1024;
 static constexpr int kThreads = 1024;                       // count, scan and scatter workgroups
-static constexpr int kCountPer = 32;                        // edges per thread of the count pass
-static constexpr int kScatterPer = 16;                      // edges per thread of the scatter pass
-static constexpr int kScatterChunk = kThreads * kScatterPer;  // 16 Ki edges per scatter workgroup
+static constexpr int kScatterPer = 8;                       // edges per thread and chunk
+static constexpr int kChunk = kThreads * kScatterPer;       // 8 Ki edges per chunk
+static constexpr int kCountChunks = 4;                      // chunks per count workgroup
+static constexpr int kGroupChunks = 128;                    // chunks per group of the offset scan
+static constexpr int kOffThreads = 256;                     // offsets workgroup: 4 waves x 32 chunks x 64 blocks
+static constexpr int kOffRows = kGroupChunks / (kOffThreads / 64);
+static constexpr unsigned kXcds = 8;                        // accelerator complex dies of the MI355X
 // dynamic LDS of the scatter: the chunk in block order (src and dst)
-static constexpr size_t kScatterLds = (size_t)kScatterChunk * 2 * sizeof(int);
+static constexpr size_t kScatterLds = (size_t)kChunk * 2 * sizeof(int);
 
 __device__ __forceinline__ int block_of(int w, int shift, int K)
 {
@@ -41,23 +54,38 @@ __device__ __forceinline__ int block_of(int w, int shift, int K)
     return b < (unsigned)K ? (int)b : K - 1;
 }
 
+// Chunks kCountChunks * blockIdx.x + j: row j of the count matrix (K blocks)
+// each, and their sum added to the chunk group's row of `part`.
 __global__ __launch_bounds__(kThreads) void k_blk_count(const int* __restrict__ src, long long m, int shift, int K,
-                                                        int* __restrict__ hist)
+                                                        int* __restrict__ cnt, int* __restrict__ part)
 {
-    __shared__ int h[kMaxBuckets];
-    for (int i = threadIdx.x; i < K; i += kThreads) h[i] = 0;
+    __shared__ int h[kCountChunks][kMaxBuckets];
+    for (int i = threadIdx.x; i < kCountChunks * kMaxBuckets; i += kThreads) (&h[0][0])[i] = 0;
     __syncthreads();
-    const long long e0 = (long long)blockIdx.x * kThreads * kCountPer;
-    int w[kCountPer];
+    const long long c0 = (long long)blockIdx.x * kCountChunks;
+    int w[kCountChunks][kScatterPer];
 #pragma unroll
-    for (int k = 0; k < kCountPer; ++k)
-        w[k] = ld_edge(src + std::min(e0 + (long long)k * kThreads + threadIdx.x, m - 1));
+    for (int j = 0; j < kCountChunks; ++j)
 #pragma unroll
-    for (int k = 0; k < kCountPer; ++k)
-        if (e0 + (long long)k * kThreads + threadIdx.x < m) atomicAdd(&h[block_of(w[k], shift, K)], 1);
+        for (int k = 0; k < kScatterPer; ++k)
+            w[j][k] = ld_edge(src + std::min((c0 + j) * kChunk + (long long)k * kThreads + threadIdx.x, m - 1));
+#pragma unroll
+    for (int j = 0; j < kCountChunks; ++j)
+#pragma unroll
+        for (int k = 0; k < kScatterPer; ++k)
+            if ((c0 + j) * kChunk + (long long)k * kThreads + threadIdx.x < m) atomicAdd(&h[j][block_of(w[j][k], shift, K)], 1);
     __syncthreads();
-    for (int i = threadIdx.x; i < K; i += kThreads)
-        if (h[i]) atomicAdd(&hist[i], h[i]);
+    const long long nch = (m + kChunk - 1) / kChunk;
+    for (int b = threadIdx.x; b < K; b += kThreads) {
+        int sum = 0;
+#pragma unroll
+        for (int j = 0; j < kCountChunks; ++j) {
+            if (c0 + j < nch) cnt[(c0 + j) * K + b] = h[j][b];
+            sum += h[j][b];
+        }
+        // kGroupChunks is a multiple of kCountChunks: one group per workgroup
+        if (sum) atomicAdd(&part[(c0 / kGroupChunks) * K + b], sum);
+    }
 }
 
 // Inclusive scan of v over the workgroup's threads (kThreads of them);
@@ -77,30 +105,78 @@ __device__ __forceinline__ int block_inclusive_scan(int v, int* tot)
     return v + add;
 }
 
-// One workgroup: first slot of every block, and the scatter's cursors.
-__global__ __launch_bounds__(kThreads) void k_blk_scan(const int* __restrict__ hist, int K, int* __restrict__ cursor)
+// One workgroup: the first slot of every block (exclusive scan of the
+// column sums of `part`), then each row of `part` replaced by the first slot
+// of its chunk group's run of each block.
+__global__ __launch_bounds__(kThreads) void k_blk_scan(int* __restrict__ part, int groups, int K)
 {
     __shared__ int tot[kThreads / 64];
     const int b = threadIdx.x;
-    const int c = b < K ? hist[b] : 0;
-    const int incl = block_inclusive_scan(c, tot);
-    if (b < K) cursor[b] = incl - c;
+    int c = 0;
+    if (b < K) {
+#pragma unroll 8
+        for (int g = 0; g < groups; ++g) c += part[(long long)g * K + b];
+    }
+    int run = block_inclusive_scan(c, tot) - c;
+    if (b < K)
+#pragma unroll 8
+        for (int g = 0; g < groups; ++g) {
+            const long long i = (long long)g * K + b;
+            const int v = part[i];
+            part[i] = run;
+            run += v;
+        }
+}
+
+// Workgroup (x, y): blocks 64x .. 64x+63 of chunk group y.  Each wave takes
+// kOffRows consecutive chunks of the group, one block per lane, and writes
+// the first slot of every (chunk, block) run over its count.
+__global__ __launch_bounds__(kOffThreads) void k_blk_offsets(int* __restrict__ cnt, const int* __restrict__ part,
+                                                             long long nch, int K)
+{
+    __shared__ int wsum[kOffThreads / 64][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int b = blockIdx.x * 64 + lane;
+    const long long r0 = (long long)blockIdx.y * kGroupChunks + (long long)wave * kOffRows;
+    int v[kOffRows];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kOffRows; ++k) {
+        v[k] = b < K && r0 + k < nch ? cnt[(r0 + k) * K + b] : 0;
+        s += v[k];
+    }
+    wsum[wave][lane] = s;
+    __syncthreads();
+    if (b >= K) return;
+    int run = part[(long long)blockIdx.y * K + b];
+    for (int k = 0; k < wave; ++k) run += wsum[k][lane];
+#pragma unroll
+    for (int k = 0; k < kOffRows; ++k) {
+        if (r0 + k < nch) cnt[(r0 + k) * K + b] = run;
+        run += v[k];
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_blk_scatter(const int* __restrict__ src, const int* __restrict__ dst,
-                                                          long long m, int shift, int K, int* __restrict__ cursor,
+                                                          long long m, int shift, int K, const int* __restrict__ off,
                                                           int* __restrict__ osrc, int* __restrict__ odst)
 {
     extern __shared__ __align__(16) int lds[];
     int* out_s = lds;
-    int* out_d = lds + kScatterChunk;
+    int* out_d = lds + kChunk;
     __shared__ int cnt[kMaxBuckets];    // edges of the chunk per block, then rank cursor
     __shared__ int lstart[kMaxBuckets]; // first position of each block in the chunk
     __shared__ int gbase[kMaxBuckets];  // first global slot of the chunk's run of each block
     __shared__ int tot[kThreads / 64];
     const int t = threadIdx.x;
-    const long long e0 = (long long)blockIdx.x * kScatterChunk;
-    const int len = (int)std::min<long long>(kScatterChunk, m - e0);
+    // Workgroups go to the XCDs in turn; XCD x takes the x-th eighth of the
+    // chunks in order, so the runs that neighbouring chunks write next to
+    // each other meet in one L2 and leave it as whole lines.
+    const unsigned per = gridDim.x / kXcds, rem = gridDim.x % kXcds;
+    const unsigned x = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
+    const long long chunk = (long long)x * per + std::min(x, rem) + j;
+    const long long e0 = chunk * kChunk;
+    const int len = (int)std::min<long long>(kChunk, m - e0);
     for (int i = t; i < K; i += kThreads) cnt[i] = 0;
     int es[kScatterPer], ed[kScatterPer];
 #pragma unroll
@@ -120,7 +196,7 @@ __global__ __launch_bounds__(kThreads) void k_blk_scatter(const int* __restrict_
     const int incl = block_inclusive_scan(c, tot);
     if (t < K) {
         lstart[t] = incl - c;
-        gbase[t] = c ? atomicAdd(&cursor[t], c) : 0;
+        gbase[t] = c ? off[chunk * K + t] : 0;
     }
     __syncthreads();
 #pragma unroll
@@ -141,11 +217,12 @@ __global__ __launch_bounds__(kThreads) void k_blk_scatter(const int* __restrict_
     }
 }
 
-// Zero the histogram (a kernel rather than a memset, so that the sequence
-// can be captured in a graph).
-__global__ void k_blk_zero(int* __restrict__ hist, int K)
+// Zero the chunk-group sums (a kernel rather than a memset, so that the
+// sequence can be captured in a graph).
+__global__ void k_blk_zero(int* __restrict__ part, long long count)
 {
-    for (int i = threadIdx.x; i < K; i += blockDim.x) hist[i] = 0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+        part[i] = 0;
 }
 
 void reorder_geometry(const DeviceInfo& d, long long m, int n, Reorder* r)
@@ -162,7 +239,17 @@ void reorder_geometry(const DeviceInfo& d, long long m, int n, Reorder* r)
     // every array starts on a 16-byte boundary (the sweep reads edges with
     // 16-byte loads when it can)
     const long long mp = (m + 3) & ~3LL;
-    r->elems = 2 * mp + 2 * kMaxBuckets;
+    r->chunks = (m + kChunk - 1) / kChunk;
+    r->groups = (r->chunks + kGroupChunks - 1) / kGroupChunks;
+    r->elems = 2 * mp + reorder_table_elems(*r);
+}
+
+long long reorder_table_elems(const Reorder& r) { return (r.chunks + r.groups) * r.K; }
+
+void reorder_bind_tables(Reorder* r, int* tables)
+{
+    r->cnt = tables;
+    r->part = tables + r->chunks * r->K;
 }
 
 void reorder_bind(Reorder* r, int* ws)
@@ -170,20 +257,22 @@ void reorder_bind(Reorder* r, int* ws)
     const long long mp = (r->m + 3) & ~3LL;
     r->src2 = ws;
     r->dst2 = ws + mp;
-    r->hist = ws + 2 * mp;
-    r->cursor = r->hist + kMaxBuckets;
+    reorder_bind_tables(r, ws + 2 * mp);
 }
 
 int enqueue_reorder(const Reorder& r, const int* src, const int* dst, hipStream_t stream)
 {
     if (r.m <= 0) return CONTOUR_OK;
-    const unsigned gc = (unsigned)((r.m + (long long)kThreads * kCountPer - 1) / ((long long)kThreads * kCountPer));
-    const unsigned gs = (unsigned)((r.m + kScatterChunk - 1) / kScatterChunk);
-    hipLaunchKernelGGL(k_blk_zero, dim3(1), dim3(kThreads), 0, stream, r.hist, r.K);
-    hipLaunchKernelGGL(k_blk_count, dim3(gc), dim3(kThreads), 0, stream, src, r.m, r.shift, r.K, r.hist);
-    hipLaunchKernelGGL(k_blk_scan, dim3(1), dim3(kThreads), 0, stream, (const int*)r.hist, r.K, r.cursor);
-    hipLaunchKernelGGL(k_blk_scatter, dim3(gs), dim3(kThreads), kScatterLds, stream, src, dst, r.m, r.shift, r.K,
-                       r.cursor, r.src2, r.dst2);
+    const long long pc = r.groups * r.K;
+    const unsigned gz = (unsigned)std::min<long long>((pc + 255) / 256, 1024);
+    const unsigned gc = (unsigned)((r.chunks + kCountChunks - 1) / kCountChunks);
+    hipLaunchKernelGGL(k_blk_zero, dim3(gz), dim3(256), 0, stream, r.part, pc);
+    hipLaunchKernelGGL(k_blk_count, dim3(gc), dim3(kThreads), 0, stream, src, r.m, r.shift, r.K, r.cnt, r.part);
+    hipLaunchKernelGGL(k_blk_scan, dim3(1), dim3(kThreads), 0, stream, r.part, (int)r.groups, r.K);
+    hipLaunchKernelGGL(k_blk_offsets, dim3((unsigned)((r.K + 63) / 64), (unsigned)r.groups), dim3(kOffThreads), 0,
+                       stream, r.cnt, (const int*)r.part, r.chunks, r.K);
+    hipLaunchKernelGGL(k_blk_scatter, dim3((unsigned)r.chunks), dim3(kThreads), kScatterLds, stream, src, dst, r.m,
+                       r.shift, r.K, (const int*)r.cnt, r.src2, r.dst2);
     CONTOUR_HIP(hipGetLastError());
     return CONTOUR_OK;
 }

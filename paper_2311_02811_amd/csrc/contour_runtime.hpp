@@ -104,14 +104,21 @@ struct Reorder {
     long long elems = 0;    // workspace ints needed
     int* src2 = nullptr;    // workspace: reordered edges
     int* dst2 = nullptr;
-    int* hist = nullptr;    // workspace: edges per block
-    int* cursor = nullptr;  // workspace: next free slot of each block
+    long long chunks = 0;   // 8 Ki-edge chunks of the edge list
+    long long groups = 0;   // groups of 128 chunks
+    int* cnt = nullptr;     // workspace: chunks x K edges per (chunk, block), then their first slots
+    int* part = nullptr;    // workspace: groups x K edges per (group, block), then their first slots
 };
 
 // Sizes for m edges over n > 0 vertices.
 void reorder_geometry(const DeviceInfo& d, long long m, int n, Reorder* r);
 // Point the reorder at a workspace of at least r->elems ints.
 void reorder_bind(Reorder* r, int* ws);
+// Ints of that workspace besides the grouped copy (count tables).
+long long reorder_table_elems(const Reorder& r);
+// Point only the count tables at `tables` (reorder_table_elems ints); the
+// grouped copy goes to r->src2 / r->dst2 as set by the caller.
+void reorder_bind_tables(Reorder* r, int* tables);
 // Enqueue the counting sort of (src, dst) into r.src2 / r.dst2.
 int enqueue_reorder(const Reorder& r, const int* src, const int* dst, hipStream_t stream);
 // Whether the automatic policy reorders a graph of this size.

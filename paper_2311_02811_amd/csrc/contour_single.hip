@@ -511,6 +511,29 @@ int contour_cc(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int
     return contour_cc_ex(src, dst, m, n, labels_out, nullptr, nullptr, stream);
 }
 
+int contour_group_edges(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int32_t* src_out,
+                        int32_t* dst_out, contour_stream_t stream)
+{
+    if (m < 0 || m >= 0x7fffffffLL || n <= 0) return CONTOUR_EINVAL;
+    if (m == 0) return CONTOUR_OK;
+    if (!src || !dst || !src_out || !dst_out) return CONTOUR_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    contour::DeviceInfo d;
+    int rc = contour::device_info(&d);
+    if (rc) return rc;
+    contour::Workspace* ws = nullptr;
+    rc = contour::workspace_for(s, &ws);
+    if (rc) return rc;
+    contour::Reorder ro;
+    contour::reorder_geometry(d, m, n, &ro);
+    rc = contour::workspace_scratch(ws, s, contour::reorder_table_elems(ro));
+    if (rc) return rc;
+    contour::reorder_bind_tables(&ro, ws->scratch);
+    ro.src2 = src_out;
+    ro.dst2 = dst_out;
+    return contour::enqueue_reorder(ro, src, dst, s);
+}
+
 int contour_cc_add_edges(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int32_t* labels_inout,
                          const contour_opts_t* opts, contour_stats_t* stats, contour_stream_t stream)
 {

@@ -24,7 +24,8 @@ def test_header_declares_entry_points():
     names = declared_functions()
     for need in ("contour_cc", "contour_cc_ex", "contour_batch_plan_create",
                  "contour_batch_plan_launch", "contour_batch_plan_destroy", "contour_cc_batched",
-                 "contour_status_string", "contour_last_hip_error", "contour_default_opts"):
+                 "contour_status_string", "contour_last_hip_error", "contour_default_opts",
+                 "contour_cc_add_edges", "contour_group_edges"):
         assert need in names
 
 
@@ -80,3 +81,18 @@ def test_add_edges_argument_errors_without_touching_the_device():
     o = contour.make_opts()
     o.order = 0x7fff
     assert lib.contour_cc_add_edges(None, None, 0, 0, None, ctypes.byref(o), None, None) == contour.EINVAL
+
+
+def test_group_edges_argument_errors_without_touching_the_device():
+    import paper_2311_02811_amd as contour
+    lib = contour.load()
+    p = ctypes.c_void_p(16)
+    assert lib.contour_group_edges(None, None, -1, 4, None, None, None) == contour.EINVAL
+    assert lib.contour_group_edges(p, p, 3, 0, p, p, None) == contour.EINVAL
+    assert lib.contour_group_edges(p, p, 3, -2, p, p, None) == contour.EINVAL
+    assert lib.contour_group_edges(None, p, 3, 4, p, p, None) == contour.EINVAL
+    assert lib.contour_group_edges(p, p, 3, 4, p, None, None) == contour.EINVAL
+    # slots of the grouped copy are int32
+    assert lib.contour_group_edges(p, p, 0x7fffffff, 4, p, p, None) == contour.EINVAL
+    # nothing to do
+    assert lib.contour_group_edges(None, None, 0, 4, None, None, None) == contour.OK
