@@ -9,12 +9,12 @@
 // The edge list is cut into chunks of 8 Ki edges; the grouped copy holds,
 // for every block, the chunks' edges of that block in chunk order:
 //   count    per chunk, a histogram of the blocks (LDS), written as one row
-//            of the chunk x block count matrix; per group of 128 chunks, the
-//            sums of those rows (global atomic adds, no return value);
+//            of the chunk x block count matrix;
+//   offsets  per group of 128 chunks, the offset of every (chunk, block)
+//            run inside the group's run of the block, written over the count
+//            matrix, and the group's total per block;
 //   scan     one workgroup: the first slot of every block, and from it the
 //            first slot of every (chunk group, block) run;
-//   offsets  per chunk group, the first slot of every (chunk, block) run,
-//            written over the count matrix;
 //   scatter  a workgroup loads one chunk, ranks its edges by block in LDS
 //            (LDS atomics), places them in block order in LDS and writes
 //            them out with consecutive lanes on consecutive slots (8 edges
@@ -24,8 +24,8 @@
 //            through one L2 at about the same time and leave it as whole
 //            lines.  A workgroup holds 64 KiB of LDS, so two share a CU and
 //            one's loads overlap the other's ranking and writes.
-// Every slot is known before the scatter: no workgroup waits on a global
-// atomic with a return value, and each block lists its edges chunk by chunk
+// Every slot is known before the scatter (no global atomics at all), and
+// each block lists its edges chunk by chunk
 // in input order, which on power-law graphs also saves sweeps (the edges of
 // a block keep the input's locality).
 #include <hip/hip_runtime.h>
@@ -55,9 +55,9 @@ __device__ __forceinline__ int block_of(int w, int shift, int K)
 }
 
 // Chunks kCountChunks * blockIdx.x + j: row j of the count matrix (K blocks)
-// each, and their sum added to the chunk group's row of `part`.
+// each.
 __global__ __launch_bounds__(kThreads) void k_blk_count(const int* __restrict__ src, long long m, int shift, int K,
-                                                        int* __restrict__ cnt, int* __restrict__ part)
+                                                        int* __restrict__ cnt)
 {
     __shared__ int h[kCountChunks][kMaxBuckets];
     for (int i = threadIdx.x; i < kCountChunks * kMaxBuckets; i += kThreads) (&h[0][0])[i] = 0;
@@ -76,16 +76,10 @@ __global__ __launch_bounds__(kThreads) void k_blk_count(const int* __restrict__ 
             if ((c0 + j) * kChunk + (long long)k * kThreads + threadIdx.x < m) atomicAdd(&h[j][block_of(w[j][k], shift, K)], 1);
     __syncthreads();
     const long long nch = (m + kChunk - 1) / kChunk;
-    for (int b = threadIdx.x; b < K; b += kThreads) {
-        int sum = 0;
+    for (int b = threadIdx.x; b < K; b += kThreads)
 #pragma unroll
-        for (int j = 0; j < kCountChunks; ++j) {
+        for (int j = 0; j < kCountChunks; ++j)
             if (c0 + j < nch) cnt[(c0 + j) * K + b] = h[j][b];
-            sum += h[j][b];
-        }
-        // kGroupChunks is a multiple of kCountChunks: one group per workgroup
-        if (sum) atomicAdd(&part[(c0 / kGroupChunks) * K + b], sum);
-    }
 }
 
 // Inclusive scan of v over the workgroup's threads (kThreads of them);
@@ -130,8 +124,9 @@ __global__ __launch_bounds__(kThreads) void k_blk_scan(int* __restrict__ part, i
 
 // Workgroup (x, y): blocks 64x .. 64x+63 of chunk group y.  Each wave takes
 // kOffRows consecutive chunks of the group, one block per lane, and writes
-// the first slot of every (chunk, block) run over its count.
-__global__ __launch_bounds__(kOffThreads) void k_blk_offsets(int* __restrict__ cnt, const int* __restrict__ part,
+// over each count the offset of that (chunk, block) run inside the group's
+// run of the block; the group's total per block goes to `part`.
+__global__ __launch_bounds__(kOffThreads) void k_blk_offsets(int* __restrict__ cnt, int* __restrict__ part,
                                                              long long nch, int K)
 {
     __shared__ int wsum[kOffThreads / 64][64];
@@ -148,8 +143,13 @@ __global__ __launch_bounds__(kOffThreads) void k_blk_offsets(int* __restrict__ c
     wsum[wave][lane] = s;
     __syncthreads();
     if (b >= K) return;
-    int run = part[(long long)blockIdx.y * K + b];
+    int run = 0;
     for (int k = 0; k < wave; ++k) run += wsum[k][lane];
+    if (wave == 0) {
+        int total = 0;
+        for (int k = 0; k < kOffThreads / 64; ++k) total += wsum[k][lane];
+        part[(long long)blockIdx.y * K + b] = total;
+    }
 #pragma unroll
     for (int k = 0; k < kOffRows; ++k) {
         if (r0 + k < nch) cnt[(r0 + k) * K + b] = run;
@@ -159,6 +159,7 @@ __global__ __launch_bounds__(kOffThreads) void k_blk_offsets(int* __restrict__ c
 
 __global__ __launch_bounds__(kThreads) void k_blk_scatter(const int* __restrict__ src, const int* __restrict__ dst,
                                                           long long m, int shift, int K, const int* __restrict__ off,
+                                                          const int* __restrict__ part,
                                                           int* __restrict__ osrc, int* __restrict__ odst)
 {
     extern __shared__ __align__(16) int lds[];
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(kThreads) void k_blk_scatter(const int* __restrict_
     const int incl = block_inclusive_scan(c, tot);
     if (t < K) {
         lstart[t] = incl - c;
-        gbase[t] = c ? off[chunk * K + t] : 0;
+        gbase[t] = c ? part[(chunk / kGroupChunks) * K + t] + off[chunk * K + t] : 0;
     }
     __syncthreads();
 #pragma unroll
@@ -217,18 +218,10 @@ __global__ __launch_bounds__(kThreads) void k_blk_scatter(const int* __restrict_
     }
 }
 
-// Zero the chunk-group sums (a kernel rather than a memset, so that the
-// sequence can be captured in a graph).
-__global__ void k_blk_zero(int* __restrict__ part, long long count)
-{
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
-        part[i] = 0;
-}
-
 void reorder_geometry(const DeviceInfo& d, long long m, int n, Reorder* r)
 {
     (void)d;
-    // the scatter stages 128 KiB of edges in LDS (set on the current device)
+    // the scatter stages 64 KiB of edges in LDS (set on the current device)
     (void)hipFuncSetAttribute((const void*)k_blk_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)kScatterLds);
     int shift = 0;
@@ -263,16 +256,13 @@ void reorder_bind(Reorder* r, int* ws)
 int enqueue_reorder(const Reorder& r, const int* src, const int* dst, hipStream_t stream)
 {
     if (r.m <= 0) return CONTOUR_OK;
-    const long long pc = r.groups * r.K;
-    const unsigned gz = (unsigned)std::min<long long>((pc + 255) / 256, 1024);
     const unsigned gc = (unsigned)((r.chunks + kCountChunks - 1) / kCountChunks);
-    hipLaunchKernelGGL(k_blk_zero, dim3(gz), dim3(256), 0, stream, r.part, pc);
-    hipLaunchKernelGGL(k_blk_count, dim3(gc), dim3(kThreads), 0, stream, src, r.m, r.shift, r.K, r.cnt, r.part);
-    hipLaunchKernelGGL(k_blk_scan, dim3(1), dim3(kThreads), 0, stream, r.part, (int)r.groups, r.K);
+    hipLaunchKernelGGL(k_blk_count, dim3(gc), dim3(kThreads), 0, stream, src, r.m, r.shift, r.K, r.cnt);
     hipLaunchKernelGGL(k_blk_offsets, dim3((unsigned)((r.K + 63) / 64), (unsigned)r.groups), dim3(kOffThreads), 0,
-                       stream, r.cnt, (const int*)r.part, r.chunks, r.K);
+                       stream, r.cnt, r.part, r.chunks, r.K);
+    hipLaunchKernelGGL(k_blk_scan, dim3(1), dim3(kThreads), 0, stream, r.part, (int)r.groups, r.K);
     hipLaunchKernelGGL(k_blk_scatter, dim3((unsigned)r.chunks), dim3(kThreads), kScatterLds, stream, src, dst, r.m,
-                       r.shift, r.K, (const int*)r.cnt, r.src2, r.dst2);
+                       r.shift, r.K, (const int*)r.cnt, (const int*)r.part, r.src2, r.dst2);
     CONTOUR_HIP(hipGetLastError());
     return CONTOUR_OK;
 }
