@@ -10,7 +10,8 @@
 //            spreads the workgroups over the graphs, each graph sequenced by
 //            its own task counters (the single-graph persistent loop)
 // Classes 0 and 1 take graphs from a queue ordered by decreasing edge count
-// (longest first); class 2 runs on a second stream concurrently with them.
+// (longest first).  Class 1 runs on the caller's stream; class 2 and then
+// class 0 run on a second stream concurrently with it.
 // A launch enqueues kernels and event waits only, so it can be captured into
 // a hipGraph and replayed.
 #include <hip/hip_runtime.h>
@@ -39,6 +40,11 @@ struct WgArgs {
     const Ctl* clock;  // t0 for the watchdog
     unsigned long long watchdog;
 };
+
+// Class-0 graphs up to this many vertices go to a launch whose workgroups
+// hold 64 KiB of labels (two or more share a CU); larger class-0 graphs, up
+// to the whole LDS of a CU, to a launch of their own.
+static constexpr int kLdsSmall = 16384;
 
 // ------------------------------------------------- one graph per workgroup --
 
@@ -299,18 +305,21 @@ struct contour_plan {
     int counts[3] = {0, 0, 0};
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    int* d_counters = nullptr;         // [0] class-0 queue, [1] class-1 queue, [2] class-2 cursor
+    int* d_counters = nullptr;         // queues: [0] class 0 (small LDS), [1] class 1, [3] class 0 (large
+                                       // LDS); [2] class-2 cursor
     contour::Ctl* d_clock = nullptr;   // class 0/1 watchdog clock
     contour::BatchJob* d_jobs = nullptr;  // class 0 jobs then class 1 jobs
     contour::SolveArgs* d_graphs = nullptr;  // class 2
     contour::Ctl* d_ctl = nullptr;     // class 2 control blocks
     int* d_want = nullptr;
     int* d_gidx = nullptr;
-    contour::WgArgs wg[2];
-    contour::wg_fn wg_kernel[2] = {nullptr, nullptr};
-    unsigned wg_grid[2] = {0, 0};
-    int wg_block[2] = {256, 256};
-    size_t wg_lds[2] = {0, 0};
+    // one-workgroup launches: [0] class 0 up to kLdsSmall vertices, [1] class
+    // 1, [2] class 0 above kLdsSmall vertices (the whole LDS of a CU)
+    contour::WgArgs wg[3];
+    contour::wg_fn wg_kernel[3] = {nullptr, nullptr, nullptr};
+    unsigned wg_grid[3] = {0, 0, 0};
+    int wg_block[3] = {256, 256, 256};
+    size_t wg_lds[3] = {0, 0, 0};
     contour::multi_fn multi_kernel = nullptr;
     unsigned multi_grid = 0;
     int multi_block = 256;
@@ -391,8 +400,8 @@ static int create_plan(const contour_batch_t* b, const contour_opts_t* opts, con
     if (rc) return rc;
     int lds_max = t ? t->lds_max_vertices : 0;
     if (lds_max < 0) return CONTOUR_EINVAL;
-    const int lds_cap = std::min(16384, (d.max_lds_per_block - 1024) / 4);
-    if (lds_max == 0 || lds_max > (d.max_lds_per_block - 1024) / 4) lds_max = lds_cap;
+    const int lds_cap = (d.max_lds_per_block - 1024) / 4;
+    if (lds_max == 0 || lds_max > lds_cap) lds_max = lds_cap;
     long long wg_max = t ? t->wg_max_edges : 0;
     if (wg_max < 0) return CONTOUR_EINVAL;
     if (wg_max == 0) wg_max = 1 << 19;
@@ -415,7 +424,7 @@ static int create_plan(const contour_batch_t* b, const contour_opts_t* opts, con
     std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
         return eo[x + 1] - eo[x] > eo[y + 1] - eo[y];
     });
-    std::vector<BatchJob> jobs[2];
+    std::vector<BatchJob> jobs[3];  // per one-workgroup launch (see contour_plan::wg)
     std::vector<int> big;
     for (int g : idx) {
         BatchJob j;
@@ -426,13 +435,13 @@ static int create_plan(const contour_batch_t* b, const contour_opts_t* opts, con
         j.n = (int)(vo[g + 1] - vo[g]);
         j.g = g;
         if (j.n <= lds_max)
-            jobs[0].push_back(j);
+            jobs[j.n <= kLdsSmall ? 0 : 2].push_back(j);
         else if (j.m <= wg_max)
             jobs[1].push_back(j);
         else
             big.push_back(g);
     }
-    p->counts[0] = (int)jobs[0].size();
+    p->counts[0] = (int)(jobs[0].size() + jobs[2].size());
     p->counts[1] = (int)jobs[1].size();
     p->counts[2] = (int)big.size();
 
@@ -440,42 +449,61 @@ static int create_plan(const contour_batch_t* b, const contour_opts_t* opts, con
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_clock, sizeof(Ctl));
     std::vector<BatchJob> all = jobs[0];
     all.insert(all.end(), jobs[1].begin(), jobs[1].end());
+    all.insert(all.end(), jobs[2].begin(), jobs[2].end());
     if (e == hipSuccess) e = upload(&p->d_jobs, all);
     if (e != hipSuccess) {
         free_plan(p);
         return hip_fail(e);
     }
     const unsigned long long wd = watchdog_ticks(d);
-    for (int c = 0; c < 2; ++c) {
-        WgArgs& a = p->wg[c];
+    size_t first = 0;
+    for (int u = 0; u < 3; ++u) {
+        const int c = u == 1 ? 1 : 0;  // the class whose geometry the launch uses
+        WgArgs& a = p->wg[u];
         a.stats = b->stats_out;
-        a.jobs = p->d_jobs + (c == 0 ? 0 : jobs[0].size());
-        a.njobs = (int)jobs[c].size();
-        a.counter = p->d_counters + c;
+        a.jobs = p->d_jobs + first;
+        a.njobs = (int)jobs[u].size();
+        first += jobs[u].size();
+        a.counter = p->d_counters + (u == 2 ? 3 : u);
         a.sched = r.sched;
         a.sched.order = order[c];
         a.max_sweeps = r.max_sweeps;
         a.clock = p->d_clock;
         a.watchdog = wd;
-        p->wg_block[c] = block[c];
-        p->wg_kernel[c] = pick_wg(block[c], ept[c], r.atomic, c == 0);
+        p->wg_block[u] = block[c];
+        p->wg_kernel[u] = pick_wg(block[c], ept[c], r.atomic, c == 0);
         int max_n = 0;
-        for (const BatchJob& j : jobs[c]) max_n = std::max(max_n, j.n);
-        p->wg_lds[c] = c == 0 ? sizeof(int) * (size_t)std::max(max_n, 1) : 0;
-        if (c == 0)
-            (void)hipFuncSetAttribute((const void*)p->wg_kernel[c], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)p->wg_lds[c]);
+        for (const BatchJob& j : jobs[u]) max_n = std::max(max_n, j.n);
+        p->wg_lds[u] = c == 0 ? sizeof(int) * (size_t)std::max(max_n, 1) : 0;
+        if (jobs[u].empty()) continue;
+        if (c == 0) {
+            // launches 0 and 2 share the kernel: allow the larger of the two
+            const size_t most = std::max(p->wg_lds[0], u == 2 ? p->wg_lds[2] : 0);
+            (void)hipFuncSetAttribute((const void*)p->wg_kernel[u], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)most);
+        }
         int occ = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)p->wg_kernel[c], block[c],
-                                                         p->wg_lds[c]);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)p->wg_kernel[u], block[c],
+                                                         p->wg_lds[u]);
         if (e != hipSuccess) {
             free_plan(p);
             return hip_fail(e);
         }
-        p->wg_grid[c] = (unsigned)std::max<long long>(
-            0, std::min<long long>((long long)std::max(occ, 1) * d.cus, (long long)jobs[c].size()));
+        p->wg_grid[u] = (unsigned)std::max<long long>(
+            0, std::min<long long>((long long)std::max(occ, 1) * d.cus, (long long)jobs[u].size()));
     }
 
+    // a side stream for class 2 and class 0 (default priority, like the
+    // caller's), joined back by an event
+    if (!big.empty() || (!jobs[1].empty() && jobs[0].size() + jobs[2].size() > 0)) {
+        e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            free_plan(p);
+            return hip_fail(e);
+        }
+    }
     if (!big.empty()) {
         std::vector<Ctl> zero(big.size());
         std::memset(zero.data(), 0, sizeof(Ctl) * zero.size());
@@ -514,9 +542,6 @@ static int create_plan(const contour_batch_t* b, const contour_opts_t* opts, con
         if (e == hipSuccess) e = upload(&p->d_graphs, graphs);
         if (e == hipSuccess) e = upload(&p->d_want, want);
         if (e == hipSuccess) e = upload(&p->d_gidx, big);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
         if (e != hipSuccess) {
             free_plan(p);
             return hip_fail(e);
@@ -536,9 +561,16 @@ static int launch_plan(contour_plan* p, hipStream_t stream)
     hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, stream, p->d_counters, p->d_clock);
     CONTOUR_HIP(hipGetLastError());
     const int nbig = p->counts[2];
-    if (nbig > 0) {
+    // Class 1 (the longest queue of one-workgroup solves) runs on the
+    // caller's stream; class 2 and then class 0 (large LDS first) run on the
+    // side stream beside it.  A class-1 workgroup leaves room on its CU for
+    // class-0 workgroups, so class 0 is taken off the critical path.
+    const bool fork = p->side && (nbig > 0 || (p->wg_grid[1] && (p->wg_grid[0] || p->wg_grid[2])));
+    if (fork) {
         CONTOUR_HIP(hipEventRecord(p->ev_fork, stream));
         CONTOUR_HIP(hipStreamWaitEvent(p->side, p->ev_fork, 0));
+    }
+    if (nbig > 0) {
         hipLaunchKernelGGL(k_batch_multi_prepare, dim3(p->prep_x, nbig), dim3(256), 0, p->side,
                            (const SolveArgs*)p->d_graphs);
         hipLaunchKernelGGL(p->multi_kernel, dim3(p->multi_grid), dim3(p->multi_block), 0, p->side,
@@ -547,15 +579,17 @@ static int launch_plan(contour_plan* p, hipStream_t stream)
             hipLaunchKernelGGL(k_batch_multi_stats, dim3((nbig + 63) / 64), dim3(64), 0, p->side,
                                (const SolveArgs*)p->d_graphs, (const int*)p->d_gidx, nbig, p->stats);
         CONTOUR_HIP(hipGetLastError());
-        CONTOUR_HIP(hipEventRecord(p->ev_join, p->side));
     }
-    for (int c = 1; c >= 0; --c) {
-        if (p->wg_grid[c] == 0) continue;
-        hipLaunchKernelGGL(p->wg_kernel[c], dim3(p->wg_grid[c]), dim3(p->wg_block[c]), p->wg_lds[c], stream,
-                           p->wg[c]);
+    for (int u : {1, 2, 0}) {
+        if (p->wg_grid[u] == 0) continue;
+        hipLaunchKernelGGL(p->wg_kernel[u], dim3(p->wg_grid[u]), dim3(p->wg_block[u]), p->wg_lds[u],
+                           u != 1 && fork ? p->side : stream, p->wg[u]);
         CONTOUR_HIP(hipGetLastError());
     }
-    if (nbig > 0) CONTOUR_HIP(hipStreamWaitEvent(stream, p->ev_join, 0));
+    if (fork) {
+        CONTOUR_HIP(hipEventRecord(p->ev_join, p->side));
+        CONTOUR_HIP(hipStreamWaitEvent(stream, p->ev_join, 0));
+    }
     return CONTOUR_OK;
 }
 

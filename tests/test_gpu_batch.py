@@ -191,7 +191,7 @@ def test_batched_many_multi_workgroup_graphs_repeated(contour, spec):
     exp = oracle.uf_batch(b.edge_off, b.vertex_off, b.src, b.dst)
     s, d = dev(b.src), dev(b.dst)
     plan = contour.BatchPlan(b.edge_off, b.vertex_off, s, d,
-                             tuning=contour.make_tuning(spec, 0, 65536))
+                             tuning=contour.make_tuning(spec, 16384, 65536))
     banner("classes %r" % plan.classes())
     assert plan.classes()[2] > 500
     for rep in range(4):
@@ -211,3 +211,40 @@ def test_single_graph_persistent_without_window_repeated(contour):
         for rep in range(10):
             labels, st = contour.cc_ex(s, d, 200000, reorder="off", **geo)
             assert np.array_equal(labels.cpu().numpy(), exp), (geo, rep)
+
+
+def test_class0_split_by_lds_size_with_graph_capture(contour):
+    # default bounds: class 0 holds graphs up to the whole LDS of a workgroup
+    # and runs graphs above 16384 vertices in a launch of their own; class 1
+    # runs beside them on the caller's stream
+    parts = [graphgen.grid_holes(150, 150, 0.1, 31), graphgen.er(30000, 60000, 32),
+             graphgen.grid_holes(130, 300, 0.05, 33), graphgen.er(90000, 200000, 34)]
+    ns = [22500, 30000, 39000, 90000]
+    for i in range(300):
+        parts.append(graphgen.er(50 + 7 * i, 3 * (50 + 7 * i), 100 + i))
+        ns.append(50 + 7 * i)
+    eo, vo = [0], [0]
+    for (s_, d_), n in zip(parts, ns):
+        eo.append(eo[-1] + s_.size)
+        vo.append(vo[-1] + n)
+    src = np.concatenate([p[0] for p in parts]).astype(np.int32)
+    dst = np.concatenate([p[1] for p in parts]).astype(np.int32)
+    exp = oracle.uf_batch(eo, vo, src, dst)
+    plan = contour.BatchPlan(eo, vo, dev(src), dev(dst))
+    banner("classes %r" % plan.classes())
+    assert plan.classes() == [303, 1, 0]
+    plan.launch()
+    torch.cuda.synchronize()
+    assert np.array_equal(plan.labels.cpu().numpy(), exp)
+    assert np.all(plan.stats.cpu().numpy()[:, 0] == 0)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.launch()
+    for rep in range(3):
+        plan.labels.fill_(-1)
+        x = torch.arange(1000, device="cuda").sum()   # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(x) == 499500
+        assert np.array_equal(plan.labels.cpu().numpy(), exp), rep
+    plan.close()
