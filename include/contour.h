@@ -239,7 +239,8 @@ typedef struct {
     contour_class_tuning_t cls[3];
     int32_t lds_max_vertices; /* class 0 bound, 0 or too large: as many labels as the LDS of one
                                  workgroup holds (about 40,000 on the MI355X); class-0 graphs above
-                                 16384 vertices run in a launch of their own */
+                                 16384 vertices run in a launch of their own, with the class-0 order
+                                 and 1024-thread workgroups of 4 edges per thread */
     int32_t wg_max_edges;     /* class 1 bound, 0: auto (2^19) */
 } contour_batch_tuning_t;
 

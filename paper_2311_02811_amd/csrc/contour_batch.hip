@@ -470,8 +470,15 @@ static int create_plan(const contour_batch_t* b, const contour_opts_t* opts, con
         a.max_sweeps = r.max_sweeps;
         a.clock = p->d_clock;
         a.watchdog = wd;
-        p->wg_block[u] = block[c];
-        p->wg_kernel[u] = pick_wg(block[c], ept[c], r.atomic, c == 0);
+        int ub = block[c], ue = ept[c];
+        if (u == 2) {
+            // a large-LDS workgroup has its CU to itself: the largest
+            // workgroup, four edges per thread
+            ub = 1024;
+            ue = 4;
+        }
+        p->wg_block[u] = ub;
+        p->wg_kernel[u] = pick_wg(ub, ue, r.atomic, c == 0);
         int max_n = 0;
         for (const BatchJob& j : jobs[u]) max_n = std::max(max_n, j.n);
         p->wg_lds[u] = c == 0 ? sizeof(int) * (size_t)std::max(max_n, 1) : 0;
@@ -483,7 +490,7 @@ static int create_plan(const contour_batch_t* b, const contour_opts_t* opts, con
                                       (int)most);
         }
         int occ = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)p->wg_kernel[u], block[c],
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)p->wg_kernel[u], ub,
                                                          p->wg_lds[u]);
         if (e != hipSuccess) {
             free_plan(p);
