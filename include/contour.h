@@ -223,7 +223,8 @@ typedef struct contour_plan* contour_plan_t;
  *   class 0  n <= lds_max_vertices: one workgroup solves the graph with its
  *            label array in LDS
  *   class 1  otherwise, m <= wg_max_edges: one workgroup solves the graph with
- *            its labels in global memory
+ *            its labels in global memory, the lowest ids (as many as the LDS
+ *            holds) kept in LDS for the whole solve
  *   class 2  the rest: several workgroups per graph, sequenced on device by
  *            per-graph task counters (as the persistent driver)
  * Zero fields mean "automatic".  The autotuner in the Python package measures

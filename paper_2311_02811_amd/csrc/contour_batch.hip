@@ -6,6 +6,7 @@
 //   class 0  small graphs: one workgroup per graph, label array in LDS, the
 //            whole solve inside the workgroup (barriers separate sweeps)
 //   class 1  medium graphs: one workgroup per graph, labels in global memory
+//            with the lowest ids of the graph held in LDS for the whole solve
 //   class 2  large graphs: many workgroups per graph; one persistent kernel
 //            spreads the workgroups over the graphs, each graph sequenced by
 //            its own task counters (the single-graph persistent loop)
@@ -39,6 +40,7 @@ struct WgArgs {
     int max_sweeps;
     const Ctl* clock;  // t0 for the watchdog
     unsigned long long watchdog;
+    int wcap;          // labels of a class-1 graph kept in LDS (the launch's dynamic LDS / 4; 0: none)
 };
 
 // Class-0 graphs up to this many vertices go to a launch whose workgroups
@@ -48,43 +50,63 @@ static constexpr int kLdsSmall = 16384;
 
 // ------------------------------------------------- one graph per workgroup --
 
-template <int EPT, int BLOCK, bool ATOMIC>
-__device__ __forceinline__ void wg_solve(const WgArgs& a, const BatchJob& job, int* L, bool lds)
+// The sweeps of one graph inside one workgroup (barriers between sweeps);
+// `global` when some labels live in global memory (stores drained before
+// each barrier).  Returns the solve's state.
+template <int EPT, int BLOCK, bool ATOMIC, class LAB>
+__device__ __forceinline__ int wg_sweeps(const WgArgs& a, const BatchJob& job, const LAB& lab, bool global,
+                                         int& sweep, int& last_change, int& rerr)
 {
-    for (int i = threadIdx.x; i < job.n; i += BLOCK) L[i] = i;
-    if (!lds) drain_stores();
-    __syncthreads();
     const long long tile_edges = (long long)BLOCK * EPT;
     const long long ntiles = (job.m + tile_edges - 1) / tile_edges;
-    const int* src = job.src;
-    const int* dst = job.dst;
-    int sweep = 0, last_change = 0, rerr = 0, state = ST_CONVERGED;
-    if (job.m > 0) {
-        for (;;) {
-            const int order = order_of_sweep(a.sched, sweep);
-            const bool pred = run_tiles_order<EPT, BLOCK, ATOMIC>(src, dst, L, L, 0, ntiles, 1, job.m,
-                                                                  (unsigned)job.n, order, rerr);
-            if (!lds) drain_stores();
-            const int any = uniform(__syncthreads_or(pred ? 1 : 0));
-            ++sweep;
-            if (!any) break;
-            last_change = sweep;
-            if (a.max_sweeps > 0 && sweep >= a.max_sweeps) {
-                state = ST_LIMIT;
-                break;
-            }
-            if ((sweep & 15) == 0) {
-                const bool expired = watchdog_expired(a.clock, a.watchdog);
-                if (uniform(__syncthreads_or(expired ? 1 : 0))) {
-                    state = ST_TIMEOUT;
-                    break;
-                }
-            }
+    if (job.m == 0) return ST_CONVERGED;
+    for (;;) {
+        const int order = order_of_sweep(a.sched, sweep);
+        const bool pred = run_tiles_lab<EPT, BLOCK, ATOMIC>(job.src, job.dst, lab, 0, ntiles, 1, job.m,
+                                                            (unsigned)job.n, order, rerr);
+        if (global) drain_stores();
+        const int any = uniform(__syncthreads_or(pred ? 1 : 0));
+        ++sweep;
+        if (!any) return ST_CONVERGED;
+        last_change = sweep;
+        if (a.max_sweeps > 0 && sweep >= a.max_sweeps) return ST_LIMIT;
+        if ((sweep & 15) == 0) {
+            const bool expired = watchdog_expired(a.clock, a.watchdog);
+            if (uniform(__syncthreads_or(expired ? 1 : 0))) return ST_TIMEOUT;
         }
     }
+}
+
+// One graph in one workgroup.  MODE 0: every label in LDS (class 0); MODE 1:
+// labels in global memory, the lowest a.wcap ids of them kept in LDS for the
+// whole solve (class 1; without the window when a.wcap is 0 or n >= 2^30).
+template <int EPT, int BLOCK, bool ATOMIC, int MODE>
+__device__ __forceinline__ void wg_solve(const WgArgs& a, const BatchJob& job, int* lds)
+{
+    int sweep = 0, last_change = 0, rerr = 0, state;
+    if (MODE == 0) {
+        for (int i = threadIdx.x; i < job.n; i += BLOCK) lds[i] = i;
+        __syncthreads();
+        state = wg_sweeps<EPT, BLOCK, ATOMIC>(a, job, FlatLabels{lds, lds}, false, sweep, last_change, rerr);
+        for (int i = threadIdx.x; i < job.n; i += BLOCK) job.labels[i] = lds[i];
+    } else if (a.wcap > 0 && (unsigned)job.n < (1u << 30)) {
+        const unsigned cnt = std::min((unsigned)job.n, (unsigned)a.wcap);
+        for (unsigned i = threadIdx.x; i < cnt; i += BLOCK) lds[i] = (int)i;
+        for (unsigned i = cnt + threadIdx.x; i < (unsigned)job.n; i += BLOCK) job.labels[i] = (int)i;
+        drain_stores();
+        __syncthreads();
+        const OwnedWindowLabels lab{lds, cnt, job.labels, label_buffer(job.labels, (unsigned)job.n),
+                                    (unsigned)job.n * 4u};
+        state = wg_sweeps<EPT, BLOCK, ATOMIC>(a, job, lab, true, sweep, last_change, rerr);
+        for (unsigned i = threadIdx.x; i < cnt; i += BLOCK) job.labels[i] = lds[i];
+    } else {
+        for (int i = threadIdx.x; i < job.n; i += BLOCK) job.labels[i] = i;
+        drain_stores();
+        __syncthreads();
+        state = wg_sweeps<EPT, BLOCK, ATOMIC>(a, job, FlatLabels{job.labels, job.labels}, true, sweep,
+                                              last_change, rerr);
+    }
     const int anyerr = uniform(__syncthreads_or(rerr));
-    if (lds)
-        for (int i = threadIdx.x; i < job.n; i += BLOCK) job.labels[i] = L[i];
     if (a.stats && threadIdx.x == 0) {
         contour_stats_t st;
         st.status = anyerr ? CONTOUR_ERANGE : (state == ST_CONVERGED ? CONTOUR_OK : CONTOUR_ENOCONV);
@@ -106,10 +128,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_wg(WgArgs a)
         const int j = uniform(s_job);
         if (j >= a.njobs) break;
         const BatchJob job = a.jobs[j];
-        if (LDS)
-            wg_solve<EPT, BLOCK, ATOMIC>(a, job, lds_labels, true);
-        else
-            wg_solve<EPT, BLOCK, ATOMIC>(a, job, job.labels, false);
+        wg_solve<EPT, BLOCK, ATOMIC, LDS ? 0 : 1>(a, job, lds_labels);
         __syncthreads();  // every lane has read s_job and finished with LDS
         if (threadIdx.x == 0) s_job = atomicAdd(a.counter, 1);
         __syncthreads();
@@ -282,6 +301,7 @@ int enqueue_wg_jobs(const DeviceInfo& d, const Resolved& r, const BatchJob* d_jo
         a.max_sweeps = r.max_sweeps;
         a.clock = d_clock;
         a.watchdog = watchdog_ticks(d);
+        a.wcap = 0;
         const wg_fn k = pick_wg(block, ept, r.atomic, c == 0);
         const size_t lds = c == 0 ? sizeof(int) * (size_t)std::max(max_n_lds, 1) : 0;
         if (c == 0) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -482,7 +502,16 @@ static int create_plan(const contour_batch_t* b, const contour_opts_t* opts, con
         int max_n = 0;
         for (const BatchJob& j : jobs[u]) max_n = std::max(max_n, j.n);
         p->wg_lds[u] = c == 0 ? sizeof(int) * (size_t)std::max(max_n, 1) : 0;
+        a.wcap = 0;
+        if (u == 1) {
+            // class 1: the rest of the LDS keeps the lowest ids of the graph
+            a.wcap = std::max(0, (d.max_lds_per_block - 2048) / 4) & ~63;
+            p->wg_lds[u] = sizeof(int) * (size_t)a.wcap;
+        }
         if (jobs[u].empty()) continue;
+        if (u == 1 && a.wcap > 0)
+            (void)hipFuncSetAttribute((const void*)p->wg_kernel[u], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)p->wg_lds[u]);
         if (c == 0) {
             // launches 0 and 2 share the kernel: allow the larger of the two
             const size_t most = std::max(p->wg_lds[0], u == 2 ? p->wg_lds[2] : 0);

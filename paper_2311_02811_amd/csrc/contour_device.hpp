@@ -498,6 +498,45 @@ struct WindowLabels {
     }
 };
 
+// The labels of a graph that one workgroup owns for its whole solve: ids
+// [0, cnt) in LDS, the rest in global memory G.  No other workgroup touches
+// them, so a store outside the window goes to G directly (by the write
+// mode), and the caller writes the window back when the solve ends.  Labels
+// move towards the smallest ids of their components, so after the first
+// sweep most of the deeper gathers of a chain land in the window.  Gathers
+// as in WindowLabels (LDS read plus a range-checked buffer load skipped when
+// the whole wave hits the window); n < 2^30.
+struct OwnedWindowLabels {
+    int* lds;
+    unsigned cnt;
+    int* G;
+    __amdgpu_buffer_rsrc_t rsrc;
+    unsigned oob;  // 4 n
+    __device__ __forceinline__ int ld(int x) const
+    {
+        typedef __attribute__((address_space(3))) const int* lds_ptr;
+        const unsigned i = (unsigned)x;
+        const bool in = i < cnt;
+        const int vl = ((lds_ptr)lds)[in ? i : 0];
+        int vg = 0;
+        if (__builtin_amdgcn_ballot_w64(!in) != 0)
+            vg = __builtin_amdgcn_raw_buffer_load_b32(rsrc, in ? oob : i * 4u, 0, 0);
+        return in ? vl : vg;
+    }
+    template <bool ATOMIC>
+    __device__ __forceinline__ void st(int x, int z) const
+    {
+        if ((unsigned)x < cnt) {
+            if (ATOMIC)
+                atomicMin(&lds[x], z);
+            else
+                lds[x] = z;
+        } else {
+            put<ATOMIC>(G, x, z);
+        }
+    }
+};
+
 template <int EPT, int BLOCK, bool ATOMIC>
 __device__ __forceinline__ bool run_tiles_order(const int* __restrict__ src, const int* __restrict__ dst,
                                                 const int* R, int* W, long long first, long long count,
