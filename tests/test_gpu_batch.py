@@ -40,6 +40,13 @@ def small_batch():
 FORCE_CLASSES = dict(lds_max_vertices=1500, wg_max_edges=30000)
 
 
+def graphgen_batch(eo, vo, src, dst):
+    """The CSR-of-graphs fields run_plan reads, for a hand-made batch."""
+    import types
+    return types.SimpleNamespace(edge_off=np.asarray(eo, np.int64), vertex_off=np.asarray(vo, np.int64),
+                                 src=np.ascontiguousarray(src, np.int32), dst=np.ascontiguousarray(dst, np.int32))
+
+
 def run_plan(contour, b, tuning=None, **opts):
     s, d = dev(b.src), dev(b.dst)
     plan = contour.BatchPlan(b.edge_off, b.vertex_off, s, d, tuning=tuning, **opts)
@@ -248,3 +255,55 @@ def test_class0_split_by_lds_size_with_graph_capture(contour):
         assert int(x) == 499500
         assert np.array_equal(plan.labels.cpu().numpy(), exp), rep
     plan.close()
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(order=1), dict(order=3), dict(order="full"),
+                                  dict(write="atomic")],
+                         ids=["default", "order1", "order3", "full", "atomic"])
+def test_class1_window_and_global_labels(contour, opts):
+    # every graph in class 1 (one workgroup, the lowest ~40 K ids in LDS, the
+    # rest in global memory): graphs well above the window, one exactly at its
+    # edge, ids permuted so that components' minima fall on both sides
+    parts, ns = [], []
+    for i, (kind, n) in enumerate([("er", 120000), ("grid", 300 * 400), ("er", 40704), ("er", 40705),
+                                   ("grid", 90 * 1000), ("er", 250000), ("er", 3000)]):
+        if kind == "er":
+            s_, d_ = graphgen.er(n, int(1.2 * n), 40 + i)
+        else:
+            r = 300 if n == 120000 else 90
+            s_, d_ = graphgen.grid_holes(r, n // r, 0.15, 40 + i, permute_ids=True)
+        parts.append((s_, d_))
+        ns.append(n)
+    eo, vo = [0], [0]
+    for (s_, d_), n in zip(parts, ns):
+        eo.append(eo[-1] + s_.size)
+        vo.append(vo[-1] + n)
+    src = np.concatenate([p[0] for p in parts]).astype(np.int32)
+    dst = np.concatenate([p[1] for p in parts]).astype(np.int32)
+    exp = oracle.uf_batch(eo, vo, src, dst)
+    banner("class-1 window batch %r" % opts)
+    labels, stats, classes = run_plan(contour, graphgen_batch(eo, vo, src, dst),
+                                      tuning=contour.make_tuning(None, 64, 1 << 22), **opts)
+    assert classes == [0, 7, 0]
+    assert np.array_equal(labels, exp)
+    assert np.all(stats[:, 0] == 0)
+
+
+def test_class1_window_out_of_range_ids(contour):
+    # a class-1 graph with bad ids below and above the window: they are
+    # skipped and reported, the other edges solved
+    n = 60000
+    s_, d_ = graphgen.er(n, 100000, 50)
+    s_ = s_.copy()
+    d_ = d_.copy()
+    s_[7] = n + 3
+    d_[11] = -1
+    d_[13] = 1 << 30
+    keep = np.ones(s_.size, bool)
+    keep[[7, 11, 13]] = False
+    exp = oracle.uf_labels(s_[keep], d_[keep], n)
+    labels, stats, classes = run_plan(contour, graphgen_batch([0, s_.size], [0, n], s_, d_),
+                                      tuning=contour.make_tuning(None, 64, 1 << 22))
+    assert classes == [0, 1, 0]
+    assert stats[0, 0] == contour.ERANGE
+    assert np.array_equal(labels, exp)
