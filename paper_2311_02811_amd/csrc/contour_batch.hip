@@ -301,10 +301,11 @@ int enqueue_wg_jobs(const DeviceInfo& d, const Resolved& r, const BatchJob* d_jo
         a.max_sweeps = r.max_sweeps;
         a.clock = d_clock;
         a.watchdog = watchdog_ticks(d);
-        a.wcap = 0;
+        // class 1 keeps the lowest ids of each graph in the LDS (as in a plan)
+        a.wcap = c == 1 ? std::max(0, (d.max_lds_per_block - 2048) / 4) & ~63 : 0;
         const wg_fn k = pick_wg(block, ept, r.atomic, c == 0);
-        const size_t lds = c == 0 ? sizeof(int) * (size_t)std::max(max_n_lds, 1) : 0;
-        if (c == 0) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const size_t lds = c == 0 ? sizeof(int) * (size_t)std::max(max_n_lds, 1) : sizeof(int) * (size_t)a.wcap;
+        if (lds > 0) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         int occ = 0;
         int rc = wg_occupancy(k, block, lds, &occ);
         if (rc) return rc;
