@@ -40,7 +40,7 @@ static constexpr int kMaxBuckets = 1024;
 static constexpr int kThreads = 1024;                       // count, scan and scatter workgroups
 static constexpr int kScatterPer = 8;                       // edges per thread and chunk
 static constexpr int kChunk = kThreads * kScatterPer;       // 8 Ki edges per chunk
-static constexpr int kCountChunks = 4;                      // chunks per count workgroup
+static constexpr int kCountChunks = 2;                      // chunks per count workgroup
 static constexpr int kGroupChunks = 128;                    // chunks per group of the offset scan
 static constexpr int kOffThreads = 256;                     // offsets workgroup: 4 waves x 32 chunks x 64 blocks
 static constexpr int kOffRows = kGroupChunks / (kOffThreads / 64);
