@@ -14,6 +14,10 @@ Contents
                            relabelled to minimum ids (a library route).
   uf_batch                 per-graph local labels of a CSR-of-graphs batch.
   check_labels             the invariants of a converged label array.
+  contour_omp              the paper's own multicore CPU design (Algorithm 1,
+                           asynchronous, early check, no atomics; Section
+                           III-B) on all host threads: the timed CPU Contour
+                           baseline, checked against uf_labels.
   contour_model            the algorithm itself (Def. 1-3, Alg. 1, the
                            asynchronous variant of Section III-B), for sweep
                            counts and per-iteration states.
@@ -29,7 +33,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cc_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_OMP_SRC = os.path.join(_HERE, "contour_omp.c")
+_OMP_PATH = os.path.join(_HERE, "libcontour_omp.so")
 _lib = None
+_omp = None
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _i64p = ctypes.POINTER(ctypes.c_int64)
 
@@ -41,6 +48,11 @@ def build(force: bool = True) -> str:
         subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp,
                                _SRC])
         os.replace(tmp, _LIB_PATH)
+    if force or not os.path.exists(_OMP_PATH):
+        tmp = _OMP_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall",
+                               "-o", tmp, _OMP_SRC])
+        os.replace(tmp, _OMP_PATH)
     return _LIB_PATH
 
 
@@ -78,6 +90,36 @@ def _call(fn, src, dst, n):
     if rc != 0:
         raise ValueError("oracle rejected the input (rc=%d): bad size or id outside [0, n)" % rc)
     return labels
+
+
+def _load_omp():
+    global _omp
+    if _omp is not None:
+        return _omp
+    if not os.path.exists(_OMP_PATH):
+        build(force=False)
+    lib = ctypes.CDLL(_OMP_PATH)
+    lib.contour_omp_cc.restype = ctypes.c_int
+    lib.contour_omp_cc.argtypes = [_i32p, _i32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                   _i32p, _i32p, _i32p]
+    _omp = lib
+    return lib
+
+
+def contour_omp(src, dst, n: int, order: int = 2):
+    """The paper's CPU design of Contour on all OpenMP threads (MM^order,
+    order 0 = chase to the root).  Returns (labels, sweeps, threads)."""
+    src, dst = _as32(src), _as32(dst)
+    if src.shape != dst.shape:
+        raise ValueError("src and dst differ in length")
+    labels = np.empty(max(n, 0), np.int32)
+    sw, nt = ctypes.c_int32(0), ctypes.c_int32(0)
+    rc = _load_omp().contour_omp_cc(src.ctypes.data_as(_i32p), dst.ctypes.data_as(_i32p), src.size, n,
+                                    int(order), labels.ctypes.data_as(_i32p), ctypes.byref(sw),
+                                    ctypes.byref(nt))
+    if rc != 0:
+        raise ValueError("contour_omp rejected the input (rc=%d)" % rc)
+    return labels, int(sw.value), int(nt.value)
 
 
 def uf_labels(src, dst, n: int) -> np.ndarray:

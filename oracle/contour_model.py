@@ -218,7 +218,7 @@ def paper_check(L: list, w: int, v: int) -> bool:
 
 
 def contour_lost_update(src, dst, n: int, order: int = 2, group: int = 8, seed: int = 0,
-                        max_sweeps: int = 1 << 20):
+                        max_sweeps: int = 1 << 20, record: bool = False):
     """Asynchronous Contour with plain stores and lost updates.
 
     Edges are processed in groups: every edge of a group reads its chains from
@@ -226,7 +226,8 @@ def contour_lost_update(src, dst, n: int, order: int = 2, group: int = 8, seed: 
     value exceeded z) are applied in a shuffled order, unconditionally, so a
     later store can overwrite a smaller value stored by an earlier one.
     Returns (labels, sweeps, invariant_ok) where invariant_ok records that
-    L[x] <= x held after every group.
+    L[x] <= x held after every group; with record set, a fourth item lists
+    the array after each sweep.
     """
     rng = random.Random(seed)
     src = [int(a) for a in src]
@@ -234,6 +235,7 @@ def contour_lost_update(src, dst, n: int, order: int = 2, group: int = 8, seed: 
     L = list(range(n))
     ok = True
     m = len(src)
+    states = []
     for s in range(max_sweeps):
         active = False
         for g0 in range(0, m, group):
@@ -249,7 +251,11 @@ def contour_lost_update(src, dst, n: int, order: int = 2, group: int = 8, seed: 
                 L[x] = z
             if any(L[x] > x for x in range(n)):
                 ok = False
+        if record:
+            states.append(np.asarray(L, np.int32))
         if not active:
+            if record:
+                return np.asarray(L, np.int32), s + 1, ok, states
             return np.asarray(L, np.int32), s + 1, ok
     raise RuntimeError("no convergence within %d sweeps" % max_sweeps)
 

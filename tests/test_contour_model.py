@@ -314,3 +314,96 @@ def test_add_edges_needs_the_ties_to_old_roots():
 
 def test_flatten_of_a_chain():
     assert np.array_equal(cm.flatten([0, 0, 1, 2, 3, 5]), [0, 0, 0, 0, 0, 5])
+
+
+# --------------------------------------------------- schedule closed forms --
+# tests/golden/schedule_closed_forms.txt holds hand-derived iteration counts
+# and per-iteration states of the operator schedules of Section III-B-4 on
+# the increasing-id path (derivations in that file's header).
+
+def schedule_cases():
+    out = []
+    with open(os.path.join(GOLDEN, "schedule_closed_forms.txt")) as f:
+        for line in f:
+            if not line.strip() or line.startswith("#"):
+                continue
+            name, n, changing, states = [p.strip() for p in line.split("|")]
+            out.append((name, int(n), int(changing), [int(d) for d in states.split(";")]))
+    return out
+
+
+def schedule_by_name(name):
+    # the two variants that are not the paper's serve as planted mistakes:
+    # a schedule that starts with order m, and C-11mm with k1 off by one
+    if name == "C-m1m1":
+        return lambda s: 1024 if s % 2 == 0 else 1
+    if name.startswith("C-11mm-k1="):
+        return cm.schedule("C-11mm", m=1024, k1=int(name.split("=")[1]))
+    return cm.schedule(name, m=1024, k1=2)
+
+
+@pytest.mark.parametrize("case", schedule_cases(), ids=lambda c: "%s-n%d" % c[:2])
+def test_schedule_closed_forms_on_the_path(case):
+    name, n, changing, offs = case
+    src, dst = family("path", n)
+    labels, iters, chg, states = cm.contour_sync(src, dst, n, schedule_by_name(name), record=True)
+    assert chg == changing and iters == changing + 1
+    assert np.all(labels == 0)
+    for k, d in enumerate(offs):
+        assert np.array_equal(states[k], np.maximum(0, np.arange(n) - d) if d else np.zeros(n)), (name, k)
+
+
+def test_swapped_schedules_fail_the_closed_forms():
+    # the closed forms tell the paper's schedules apart from their plausible
+    # mistakes on n = 9: C-1m1m started with order m, C-11mm with k1 off by
+    # one either way, and the two schedules swapped all change the count
+    src, dst = family("path", 9)
+    counts = {name: cm.contour_sync(src, dst, 9, schedule_by_name(name))[2]
+              for name in ("C-11mm", "C-1m1m", "C-m1m1", "C-11mm-k1=1", "C-11mm-k1=3")}
+    assert counts["C-1m1m"] == 2 and counts["C-m1m1"] == 3
+    assert counts["C-11mm"] == 3 and counts["C-11mm-k1=1"] == 2 and counts["C-11mm-k1=3"] == 4
+    assert counts["C-11mm"] != counts["C-1m1m"]
+
+
+# ------------------------------------------------ asynchronous closed form --
+# Section III-B-1: the update is in place, so a later edge of the same sweep
+# reads what an earlier one stored.  Increasing-id path, order 1:
+#   edges in increasing order <0,1>, <1,2>, ...: edge <j-1, j> reads
+#   L[j-1] = 0 stored by the edge before it, so one sweep maps every vertex
+#   to 0 (1 changing sweep, then one that changes nothing);
+#   edges in decreasing order: edge <j-1, j> runs before <j-2, j-1> has
+#   lowered L[j-1], so a sweep moves each label by one, exactly like the
+#   synchronous update: n - 1 changing sweeps.
+# A model that applied its stores to a copy (the synchronous update) would
+# need n - 1 sweeps in both orders.
+
+@pytest.mark.parametrize("n", [2, 3, 10, 57])
+def test_async_in_place_closed_form_on_the_path(n):
+    src, dst = family("path", n)
+    inc = list(range(n - 1))
+    lab, sweeps = cm.contour_async(src, dst, n, 1, inc)
+    assert np.all(lab == 0) and sweeps == 2
+    lab, sweeps = cm.contour_async(src, dst, n, 1, inc[::-1])
+    assert np.all(lab == 0) and sweeps == (n - 1) + 1
+
+
+# ----------------------------------------------------- lost-update pin ----
+# Section III-B-3: plain stores may lose updates.  Vertices 0, 1, 2 with the
+# edges <1, 2> and <0, 2> in one group, order 2, identity labels: edge <1, 2>
+# reads z = 1 and stores L[2] = 1, edge <0, 2> reads z = 0 and stores
+# L[2] = 0.  Applied in the order (L[2] = 0, L[2] = 1) the smaller value is
+# overwritten, so L[2] = 1 after the first sweep; in the other order L[2] = 0.
+# Either way the next sweeps reach the labels [0, 0, 0].  A model whose
+# stores took the minimum (nothing lost) would always show L[2] = 0.
+
+def test_lost_update_model_really_loses_stores():
+    src, dst = np.array([1, 0]), np.array([2, 2])
+    after_first = set()
+    for seed in range(40):
+        lab, sweeps, ok, states = cm.contour_lost_update(src, dst, 3, 2, group=8, seed=seed, record=True)
+        assert ok and np.array_equal(lab, [0, 0, 0])
+        after_first.add(int(states[0][2]))
+        if states[0][2] == 1:
+            # the lost store costs a sweep: sweep 2 repairs L[2], sweep 3 checks
+            assert sweeps == 3
+    assert after_first == {0, 1}

@@ -187,6 +187,29 @@ def test_sync_mode_matches_algorithm1_sweep_by_sweep(contour):
         assert st.sweeps_executed == iters and st.status == 0
 
 
+@pytest.mark.parametrize("sched,k1", [("11mm", 2), ("1m1m", 2), ("11mm", 3)])
+def test_sync_mode_schedules_match_algorithm1_sweep_by_sweep(contour, sched, k1):
+    # Operator schedules of Section III-B-4 under the synchronous update: the
+    # order changes from one iteration to the next, and after every iteration
+    # the GPU state equals the model's (C-11mm with k1 order-1 iterations
+    # first, C-1m1m alternating from order 1; the paper's m = 1024).  The path
+    # with increasing ids is one of the graphs: its states are the closed
+    # forms of tests/golden/schedule_closed_forms.txt.
+    graphs = [(np.arange(63, dtype=np.int32), np.arange(1, 64, dtype=np.int32), 64),
+              (*graphgen.grid_holes(40, 37, 0.15, 9, permute_ids=True), 40 * 37)]
+    name = "C-11mm" if sched == "11mm" else "C-1m1m"
+    for src, dst, n in graphs:
+        _, iters, _, states = cm.contour_sync(src, dst, n, cm.schedule(name, m=1024, k1=k1), record=True)
+        for k in range(1, iters + 1):
+            banner("sync %s k1=%d n=%d after %d of %d iterations" % (sched, k1, n, k, iters))
+            got, st = solve(contour, src, dst, n, driver="hostloop", update="sync", write="atomic",
+                            order=1024, schedule=sched, k1=k1, max_sweeps=k)
+            assert np.array_equal(got, states[k - 1]), (sched, k1, n, k)
+        got, st = solve(contour, src, dst, n, driver="hostloop", update="sync", write="atomic",
+                        order=1024, schedule=sched, k1=k1)
+        assert st.sweeps_executed == iters and st.status == 0
+
+
 def test_edge_cases(contour):
     e = np.zeros(0, np.int32)
     got, st = solve(contour, e, e, 0)
@@ -242,6 +265,42 @@ def test_sweep_limit_and_warm_start_resume(contour):
         lab2, st2 = contour.cc_ex(s, d, n, labels=lab, warm_start=True, **mode)
         assert np.array_equal(lab2.cpu().numpy(), exp)
         assert contour.read_stats(st2).status == 0
+
+
+@pytest.mark.parametrize("mode", [dict(), dict(reorder="on"), dict(order=3), dict(order="full"),
+                                  dict(write="atomic"), dict(driver="hostloop")],
+                         ids=["default", "reorder", "order3", "full", "atomic", "hostloop"])
+def test_async_states_keep_the_invariants_sweep_by_sweep(contour, mode):
+    # Snapshots of the asynchronous update one sweep at a time (a sweep limit
+    # of 1, then a warm start from the snapshot): at every snapshot
+    # L[x] <= x and L[x] lies in x's component (the invariants of
+    # Section II-A that every conditional assignment keeps), labels never
+    # rise from one snapshot to the next, and the chain ends once a sweep
+    # leaves the state unchanged, at the oracle's labels.
+    for (src, dst), n in ((graphgen.grid_holes(300, 200, 0.1, 4, permute_ids=True), 60000),
+                          (graphgen.rmat(16, 8, 6), 1 << 16)):
+        exp = oracle.uf_labels(src, dst, n)
+        ids = np.arange(n)
+        s, d = dev(src), dev(dst)
+        lab = torch.arange(n, dtype=torch.int32, device="cuda")
+        prev = ids.astype(np.int32)
+        for k in range(1, 64):
+            banner("snapshot %r n=%d sweep %d" % (mode, n, k))
+            lab, st = contour.cc_ex(s, d, n, labels=lab, warm_start=True, max_sweeps=1, **mode)
+            torch.cuda.synchronize()
+            cur = lab.cpu().numpy()
+            stats = contour.read_stats(st)
+            assert np.all(cur <= ids) and np.all(cur >= 0), (mode, k)
+            assert np.array_equal(exp[cur], exp), (mode, k)
+            assert np.all(cur <= prev), (mode, k)
+            if stats.status == contour.OK:
+                # the sweep found nothing to change: converged
+                assert np.array_equal(cur, prev) and np.array_equal(cur, exp), (mode, k)
+                break
+            assert stats.status == contour.ENOCONV
+            prev = cur
+        else:
+            pytest.fail("no convergence in 63 single-sweep steps")
 
 
 def test_bad_warm_start_is_rejected(contour):
