@@ -29,6 +29,13 @@
  *     NULL for the null stream) and return before it completes, except where
  *     a driver mode says it blocks.  Results are valid once the stream has
  *     completed the enqueued work.
+ *   * The library keeps a workspace per (device, stream): a control block and
+ *     a grow-only scratch array.  The first call on a stream, and a call that
+ *     needs more scratch than the stream holds, allocate it (and synchronise
+ *     the stream before growing it).  contour_reserve does that up front;
+ *     after it, calls within the reserved sizes only enqueue kernels (no
+ *     allocation, no synchronisation, no memset), so they can be captured into
+ *     a hipGraph.
  *   * Argument errors (NULL with a non-zero size, negative sizes, bad
  *     options) are returned synchronously and nothing is enqueued.
  *   * Data errors are reported through contour_stats_t.status after the
@@ -157,6 +164,19 @@ int contour_cc(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
 int contour_cc_ex(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
                   int32_t* labels_inout, const contour_opts_t* opts, contour_stats_t* stats,
                   contour_stream_t stream);
+
+/* contour_reserve: allocate, up front, the workspace that contour_cc,
+ * contour_cc_ex (persistent driver) and contour_group_edges need on `stream`
+ * for graphs of up to m edges and n vertices under `opts` (NULL: defaults):
+ * the stream's control block and scratch (the grouped copy of the edges and
+ * the grouping's count tables, about 8.5 m bytes when the options group the
+ * edges).  It blocks (it may synchronise the stream and allocate); later calls
+ * on the stream within these sizes enqueue only kernels and may be captured.
+ * Reserving less than the stream already holds keeps what it holds.
+ * contour_cc_add_edges and the host-loop driver keep their own behaviour.
+ * Returns CONTOUR_OK, CONTOUR_EINVAL, CONTOUR_ENOTSUP, CONTOUR_ENOMEM or
+ * CONTOUR_EHIP. */
+int contour_reserve(int64_t m, int32_t n, const contour_opts_t* opts, contour_stream_t stream);
 
 /* contour_group_edges: the edge list grouped by source block, as a solve that
  * reorders prepares it before its first sweep (the asynchronous update of

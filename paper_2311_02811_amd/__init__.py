@@ -128,6 +128,16 @@ def cc_ex(src, dst, n: int, labels=None, stream=None, stats: bool = True, **opts
     return labels, st
 
 
+def reserve(m: int, n: int, stream=None, **opts):
+    """contour_reserve: allocate the stream's workspace for graphs of up to m
+    edges and n vertices, so that later solves on the stream within these
+    sizes only enqueue kernels (and can be captured into a graph)."""
+    o = make_opts(**opts)
+    rc = load().contour_reserve(int(m), int(n), ctypes.byref(o), _stream_ptr(stream))
+    if rc != OK:
+        raise ContourError(rc, "contour_reserve")
+
+
 def group_edges(src, dst, n: int, stream=None):
     """contour_group_edges: (src_out, dst_out), the edge list grouped by source
     block as a reordering solve prepares it (stream ordered)."""

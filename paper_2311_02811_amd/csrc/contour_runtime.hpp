@@ -123,6 +123,8 @@ void reorder_bind_tables(Reorder* r, int* tables);
 int enqueue_reorder(const Reorder& r, const int* src, const int* dst, hipStream_t stream);
 // Whether the automatic policy reorders a graph of this size.
 inline bool reorder_auto(long long m, int n) { return n > (1 << 20) && m >= (1 << 20); }
+// Whether a solve with these options groups its edges first.
+bool wants_reorder(const Resolved& r, long long m, int n);
 
 // A prepared single-graph persistent solve: everything needed to enqueue it
 // without allocating (used by contour_cc_ex and by batched plans).
@@ -151,6 +153,11 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r, const int* src, c
 // persistent sweep kernel, write stats.  Optional events bracket the sweeps.
 int enqueue_persistent(const PersistentLaunch& p, contour_stats_t* stats, hipStream_t stream,
                        hipEvent_t ev_begin, hipEvent_t ev_end);
+
+// Enqueue the statistics of a solve with no vertices: status OK, or
+// CONTOUR_ERANGE when range_err (there were edges, so some id lies outside
+// [0, 0)).  ctl is reset first.
+int enqueue_empty_stats(Ctl* ctl, contour_stats_t* stats, int range_err, hipStream_t stream);
 
 // Validate opts and fill defaults; returns CONTOUR_OK or CONTOUR_EINVAL /
 // CONTOUR_ENOTSUP.

@@ -202,7 +202,7 @@ static void pick_kernels(int block, int ept, bool atomic, persistent_fn* p, swee
     else pick_w<false>(block, ept, atomic, p, s);
 }
 
-static bool wants_reorder(const Resolved& r, long long m, int n)
+bool wants_reorder(const Resolved& r, long long m, int n)
 {
     if (m >= 0x7fffffffLL) return false;  // slots of the counting sort are int32
     if (r.reorder == CONTOUR_REORDER_ON) return true;
@@ -357,6 +357,14 @@ int enqueue_persistent(const PersistentLaunch& p, contour_stats_t* stats, hipStr
     return CONTOUR_OK;
 }
 
+int enqueue_empty_stats(Ctl* ctl, contour_stats_t* stats, int range_err, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, stream, ctl);
+    hipLaunchKernelGGL(k_write_stats, dim3(1), dim3(64), 0, stream, (const Ctl*)ctl, stats, range_err);
+    CONTOUR_HIP(hipGetLastError());
+    return CONTOUR_OK;
+}
+
 // Host-sequenced sweeps (asynchronous or synchronous update).  Blocks the
 // calling thread: it reads the control block every few sweeps.
 static int run_hostloop(const DeviceInfo& d, const Resolved& r0, const int* src, const int* dst,
@@ -496,13 +504,34 @@ int contour_cc_ex(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, 
         contour::Workspace* ws = nullptr;
         rc = contour::workspace_for((hipStream_t)stream, &ws);
         if (rc) return rc;
-        hipLaunchKernelGGL(contour::k_reset_ctl, dim3(1), dim3(64), 0, (hipStream_t)stream, ws->ctl);
-        hipLaunchKernelGGL(contour::k_write_stats, dim3(1), dim3(64), 0, (hipStream_t)stream,
-                           (const contour::Ctl*)ws->ctl, stats, m > 0 ? 1 : 0);
-        CONTOUR_HIP(hipGetLastError());
-        return CONTOUR_OK;
+        return contour::enqueue_empty_stats(ws->ctl, stats, m > 0 ? 1 : 0, (hipStream_t)stream);
     }
     return contour::run_solve(src, dst, m, n, labels_inout, r, stats, (hipStream_t)stream);
+}
+
+int contour_reserve(int64_t m, int32_t n, const contour_opts_t* opts, contour_stream_t stream)
+{
+    if (m < 0 || n < 0) return CONTOUR_EINVAL;
+    contour::Resolved r;
+    int rc = contour::resolve_opts(opts, &r);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    contour::Workspace* ws = nullptr;
+    rc = contour::workspace_for(s, &ws);
+    if (rc) return rc;
+    if (n == 0 || m == 0) return CONTOUR_OK;
+    contour::DeviceInfo d;
+    rc = contour::device_info(&d);
+    if (rc) return rc;
+    // what run_solve, run_hostloop and contour_group_edges ask of the scratch
+    long long need = r.sync ? n : 0;
+    if (m < 0x7fffffffLL) {
+        contour::Reorder ro;
+        contour::reorder_geometry(d, m, n, &ro);
+        if (contour::wants_reorder(r, m, n)) need += ro.elems;
+        need = std::max(need, contour::reorder_table_elems(ro));
+    }
+    return contour::workspace_scratch(ws, s, need);
 }
 
 int contour_cc(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int32_t* labels_out,

@@ -96,3 +96,13 @@ def test_group_edges_argument_errors_without_touching_the_device():
     assert lib.contour_group_edges(p, p, 0x7fffffff, 4, p, p, None) == contour.EINVAL
     # nothing to do
     assert lib.contour_group_edges(None, None, 0, 4, None, None, None) == contour.OK
+
+
+def test_reserve_argument_errors_without_touching_the_device():
+    import paper_2311_02811_amd as contour
+    lib = contour.load()
+    assert lib.contour_reserve(-1, 4, None, None) == contour.EINVAL
+    assert lib.contour_reserve(4, -1, None, None) == contour.EINVAL
+    o = contour.make_opts()
+    o.order = 5000
+    assert lib.contour_reserve(4, 4, ctypes.byref(o), None) == contour.EINVAL
