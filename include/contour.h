@@ -35,7 +35,7 @@
  *     the stream before growing it).  contour_reserve does that up front;
  *     after it, calls within the reserved sizes only enqueue kernels (no
  *     allocation, no synchronisation, no memset), so they can be captured into
- *     a hipGraph.
+ *     a hipGraph.  contour_cc_noalloc never allocates at all.
  *   * Argument errors (NULL with a non-zero size, negative sizes, bad
  *     options) are returned synchronously and nothing is enqueued.
  *   * Data errors are reported through contour_stats_t.status after the
@@ -67,7 +67,8 @@ typedef enum {
     CONTOUR_ENOMEM = 3,  /* device allocation of the workspace failed */
     CONTOUR_EHIP = 4,    /* a HIP runtime call failed */
     CONTOUR_ENOCONV = 5, /* max_sweeps reached before convergence (stats) */
-    CONTOUR_ENOTSUP = 6  /* option combination not supported */
+    CONTOUR_ENOTSUP = 6, /* option combination not supported */
+    CONTOUR_ETOOBIG = 7  /* the input needs more scratch than contour_cc_noalloc's fixed array */
 } contour_status_t;
 
 /* Operator order h of MM^h (Definition 3).  1, 2 (default), 3, ... up to
@@ -177,6 +178,34 @@ int contour_cc_ex(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
  * Returns CONTOUR_OK, CONTOUR_EINVAL, CONTOUR_ENOTSUP, CONTOUR_ENOMEM or
  * CONTOUR_EHIP. */
 int contour_reserve(int64_t m, int32_t n, const contour_opts_t* opts, contour_stream_t stream);
+
+/* contour_cc_noalloc: contour_cc_ex for callers that cannot allocate device
+ * memory -- code under hipGraph stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  It calls no hipMalloc, hipFree or allocating library
+ * routine: the solve's scratch (its control block and, when the edges are
+ * grouped, the grouped copy and the grouping's count tables) is one fixed
+ * device array of CONTOUR_NOALLOC_SCRATCH_BYTES per device, held by the library
+ * until the process ends.
+ *   arguments   as contour_cc_ex (same meaning, layout and ownership)
+ *   limits      the persistent driver only (CONTOUR_DRIVER_HOSTLOOP gives
+ *               CONTOUR_ENOTSUP, and so does CONTOUR_UPDATE_SYNC, as for
+ *               contour_cc_ex).  Grouping the edges needs about 8.5 m bytes of
+ *               the array (8 m for the grouped copy, m / 2 for the count
+ *               tables), so up to about 3.9 million edges are grouped: with
+ *               CONTOUR_REORDER_AUTO a graph whose grouped copy does not fit is
+ *               solved without grouping (same labels, slower); with
+ *               CONTOUR_REORDER_ON it is refused with CONTOUR_ETOOBIG and nothing
+ *               is enqueued.
+ *   races       every call on one device shares that device's array, and each
+ *               call resets it when its work starts on the device: calls whose
+ *               work can overlap on one device (different streams, or host
+ *               threads without ordering) race and give wrong results; calls on
+ *               one stream are ordered by the stream.
+ * Returns as contour_cc_ex, or CONTOUR_ETOOBIG. */
+#define CONTOUR_NOALLOC_SCRATCH_BYTES (32u << 20)
+int contour_cc_noalloc(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
+                       int32_t* labels_inout, const contour_opts_t* opts, contour_stats_t* stats,
+                       contour_stream_t stream);
 
 /* contour_group_edges: the edge list grouped by source block, as a solve that
  * reorders prepares it before its first sweep (the asynchronous update of

@@ -25,7 +25,7 @@ _UPDATE = {"async": 0, "sync": 1}
 _DRIVER = {"persistent": 0, "hostloop": 1}
 _REORDER = {"auto": 0, "off": 1, "on": 2}
 
-OK, EINVAL, ERANGE, ENOMEM, EHIP, ENOCONV, ENOTSUP = range(7)
+OK, EINVAL, ERANGE, ENOMEM, EHIP, ENOCONV, ENOTSUP, ETOOBIG = range(8)
 
 
 class ContourError(RuntimeError):
@@ -136,6 +136,22 @@ def reserve(m: int, n: int, stream=None, **opts):
     rc = load().contour_reserve(int(m), int(n), ctypes.byref(o), _stream_ptr(stream))
     if rc != OK:
         raise ContourError(rc, "contour_reserve")
+
+
+def cc_noalloc(src, dst, n: int, labels, stats, stream=None, **opts):
+    """contour_cc_noalloc: as cc_ex, but the library allocates nothing (its
+    scratch is a fixed device array shared by every call on the device).
+    `labels` (int32[n]) and `stats` (int32[4] or None) are caller-owned CUDA
+    tensors; the call only enqueues work."""
+    _check_edges(src, dst)
+    o = make_opts(**opts)
+    rc = load().contour_cc_noalloc(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                   src.numel(), int(n), ctypes.c_void_p(labels.data_ptr()),
+                                   ctypes.byref(o), ctypes.c_void_p(stats.data_ptr() if stats is not None else 0),
+                                   _stream_ptr(stream))
+    if rc != OK:
+        raise ContourError(rc, "contour_cc_noalloc")
+    return labels, stats
 
 
 def group_edges(src, dst, n: int, stream=None):

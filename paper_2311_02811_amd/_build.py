@@ -23,6 +23,7 @@ SOURCES = [
     "contour_batch.hip",
     "contour_reorder.hip",
     "contour_serve.cpp",
+    "contour_noalloc.hip",
 ]
 
 HIPCC_FLAGS = [

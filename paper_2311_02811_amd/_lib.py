@@ -73,6 +73,9 @@ SIGNATURES = {
                                             ctypes.c_void_p, ctypes.c_void_p]),
     "contour_reserve": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ContourOpts),
                                        ctypes.c_void_p]),
+    "contour_cc_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                          ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ContourOpts),
+                                          ctypes.c_void_p, ctypes.c_void_p]),
     "contour_group_edges": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "contour_status_string": (ctypes.c_char_p, [ctypes.c_int]),

@@ -196,6 +196,7 @@ const char* contour_status_string(int s)
     case CONTOUR_EHIP: return "HIP runtime error";
     case CONTOUR_ENOCONV: return "sweep limit reached before convergence";
     case CONTOUR_ENOTSUP: return "option combination not supported";
+    case CONTOUR_ETOOBIG: return "input needs more than the fixed no-allocation scratch";
     default: return "unknown status";
     }
 }

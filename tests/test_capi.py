@@ -98,7 +98,7 @@ def test_group_edges_argument_errors_without_touching_the_device():
     assert lib.contour_group_edges(None, None, 0, 4, None, None, None) == contour.OK
 
 
-def test_reserve_argument_errors_without_touching_the_device():
+def test_reserve_and_noalloc_argument_errors_without_touching_the_device():
     import paper_2311_02811_amd as contour
     lib = contour.load()
     assert lib.contour_reserve(-1, 4, None, None) == contour.EINVAL
@@ -106,3 +106,8 @@ def test_reserve_argument_errors_without_touching_the_device():
     o = contour.make_opts()
     o.order = 5000
     assert lib.contour_reserve(4, 4, ctypes.byref(o), None) == contour.EINVAL
+    assert lib.contour_cc_noalloc(None, None, -1, 4, None, None, None, None) == contour.EINVAL
+    assert lib.contour_cc_noalloc(None, None, 3, 4, None, None, None, None) == contour.EINVAL
+    assert lib.contour_cc_noalloc(None, None, 0, 4, None, None, None, None) == contour.EINVAL
+    assert lib.contour_cc_noalloc(None, None, 0, 0, None, ctypes.byref(o), None, None) == contour.EINVAL
+    assert lib.contour_status_string(contour.ETOOBIG).startswith(b"input needs more")
