@@ -86,12 +86,13 @@ typedef enum {
 
 /* Write rule of the conditional assignment. */
 /* CONTOUR_WRITE_PLAIN: if (read > z) L[x] = z, a benign race (Section III-B-3),
- * where memory is coherent: in LDS label windows, between the kernels of the
- * host-loop driver, and for one-workgroup batched graphs.  Inside the
- * persistent kernels the XCDs' L2 caches are not coherent for cached stores,
- * so stores into global memory there are written through or atomic minima
- * in either mode; the labels are the same, the early convergence check stays
- * sound. */
+ * in memory that one workgroup owns: LDS label windows and the labels of
+ * one-workgroup batched graphs.  Label stores that workgroups on different
+ * XCDs race on go to global memory as written-through stores or atomic
+ * minima in either mode, on every driver: the XCDs' L2 caches are not
+ * coherent for cached stores within a kernel, and plain global stores also
+ * gave a wrong result once on the host-loop driver.  The labels are the
+ * same either way and the early convergence check stays sound. */
 #define CONTOUR_WRITE_PLAIN 0
 #define CONTOUR_WRITE_ATOMIC 1 /* if (read > z) atomic_min(&L[x], z);  Eq. (cas) */
 
@@ -124,6 +125,8 @@ typedef struct {
                             before the sweeps (a radix partition on device) */
     int32_t window;      /* with reordering: labels staged in LDS per task, 0 = as many
                             as one workgroup's LDS holds; at least 1024 */
+    int32_t dst_ranges;  /* CONTOUR_DST_RANGES_*: with reordering, also group the edges by
+                            destination range and give each XCD its own ranges */
 } contour_opts_t;
 
 /* Edge reordering.  The sweeps may apply MM^h to the edges in any order
@@ -134,6 +137,16 @@ typedef struct {
 #define CONTOUR_REORDER_AUTO 0 /* on when the label array exceeds the caches of one XCD */
 #define CONTOUR_REORDER_OFF 1
 #define CONTOUR_REORDER_ON 2
+
+/* Destination ranges (persistent driver, with reordering).  A second, stable
+ * grouping pass orders the grouped edges by destination range (ranges of
+ * 2^19 ids, 2 MiB of labels, at most 64 ranges), and the sweep's tasks are
+ * dealt to the eight XCDs by segments of consecutive ranges, so the
+ * destination-side label gathers of an XCD stay in its own L2 while the
+ * source side keeps its LDS window.  Labels are identical either way. */
+#define CONTOUR_DST_RANGES_AUTO 0 /* on when the label array exceeds one XCD's L2 and m >= 4 n */
+#define CONTOUR_DST_RANGES_OFF 1
+#define CONTOUR_DST_RANGES_ON 2   /* values 16..30 also mean on, with ranges of 2^value ids */
 
 typedef struct {
     int32_t status;             /* contour_status_t of the data checks */
@@ -170,8 +183,8 @@ int contour_cc_ex(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
  * contour_cc_ex (persistent driver) and contour_group_edges need on `stream`
  * for graphs of up to m edges and n vertices under `opts` (NULL: defaults):
  * the stream's control block and scratch (the grouped copy of the edges and
- * the grouping's count tables, about 8.5 m bytes when the options group the
- * edges).  It blocks (it may synchronise the stream and allocate); later calls
+ * the grouping's count tables: about 8.5 m bytes when the options group the
+ * edges, 16.5 m with destination ranges).  It blocks (it may synchronise the stream and allocate); later calls
  * on the stream within these sizes enqueue only kernels and may be captured.
  * Reserving less than the stream already holds keeps what it holds.
  * contour_cc_add_edges and the host-loop driver keep their own behaviour.
@@ -191,7 +204,9 @@ int contour_reserve(int64_t m, int32_t n, const contour_opts_t* opts, contour_st
  *               CONTOUR_ENOTSUP, and so does CONTOUR_UPDATE_SYNC, as for
  *               contour_cc_ex).  Grouping the edges needs about 8.5 m bytes of
  *               the array (8 m for the grouped copy, m / 2 for the count
- *               tables), so up to about 3.9 million edges are grouped: with
+ *               tables), so up to about 3.9 million edges are grouped (the
+ *               second pass by destination range needs another 8 m and is
+ *               left out under CONTOUR_DST_RANGES_AUTO when it does not fit): with
  *               CONTOUR_REORDER_AUTO a graph whose grouped copy does not fit is
  *               solved without grouping (same labels, slower); with
  *               CONTOUR_REORDER_ON it is refused with CONTOUR_ETOOBIG and nothing
@@ -225,6 +240,18 @@ int contour_cc_noalloc(const int32_t* src, const int32_t* dst, int64_t m, int32_
  * CONTOUR_ENOMEM or CONTOUR_EHIP. */
 int contour_group_edges(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
                         int32_t* src_out, int32_t* dst_out, contour_stream_t stream);
+
+/* contour_group_edges_ranges: the edge list as a solve with destination
+ * ranges prepares it: grouped by source block as above, then stably by
+ * destination range r = min(dst >> t, R - 1), dst read as unsigned, where t is
+ * the smallest shift >= 19 with (n - 1) >> t < 64 and R = ((n - 1) >> t) + 1.
+ * The output lists the edges by range, within a range by source block, and
+ * within one (range, block) by the 8192-edge chunks of the input in input
+ * order.  Arguments, limits and returns as contour_group_edges, with n > 2^19
+ * (smaller n: CONTOUR_EINVAL, there would be one range); a workspace of about
+ * 8.5 m bytes is kept per (device, stream). */
+int contour_group_edges_ranges(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
+                               int32_t* src_out, int32_t* dst_out, contour_stream_t stream);
 
 /* contour_cc_add_edges: labels after adding edges to a labelled graph.
  *   src, dst      device int32[m], the new edges (ids in [0, n))

@@ -72,7 +72,8 @@ def _check_edges(src, dst):
 
 def make_opts(order=2, schedule="fixed", k1=2, write="plain", update="async",
               driver="persistent", max_sweeps=0, warm_start=False, block=0,
-              edges_per_thread=0, chunk_tiles=0, grid=0, reorder="auto", window=0) -> ContourOpts:
+              edges_per_thread=0, chunk_tiles=0, grid=0, reorder="auto", window=0,
+              dst_ranges="auto") -> ContourOpts:
     o = ContourOpts()
     load().contour_default_opts(ctypes.byref(o))
     o.order = ORDER_FULL if order in ("full", ORDER_FULL) else int(order)
@@ -89,6 +90,7 @@ def make_opts(order=2, schedule="fixed", k1=2, write="plain", update="async",
     o.grid = int(grid)
     o.reorder = _REORDER[reorder]
     o.window = int(window)
+    o.dst_ranges = int(dst_ranges) if isinstance(dst_ranges, int) else _REORDER[dst_ranges]
     return o
 
 
@@ -154,17 +156,19 @@ def cc_noalloc(src, dst, n: int, labels, stats, stream=None, **opts):
     return labels, stats
 
 
-def group_edges(src, dst, n: int, stream=None):
-    """contour_group_edges: (src_out, dst_out), the edge list grouped by source
-    block as a reordering solve prepares it (stream ordered)."""
+def group_edges(src, dst, n: int, stream=None, ranges: bool = False):
+    """contour_group_edges (or, with ranges=True, contour_group_edges_ranges):
+    (src_out, dst_out), the edge list grouped as a reordering solve prepares
+    it (stream ordered)."""
     torch = _torch()
     _check_edges(src, dst)
     so, do = torch.empty_like(src), torch.empty_like(dst)
-    rc = load().contour_group_edges(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
-                                    src.numel(), int(n), ctypes.c_void_p(so.data_ptr()),
-                                    ctypes.c_void_p(do.data_ptr()), _stream_ptr(stream))
+    lib = load()
+    fn = lib.contour_group_edges_ranges if ranges else lib.contour_group_edges
+    rc = fn(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), src.numel(), int(n),
+            ctypes.c_void_p(so.data_ptr()), ctypes.c_void_p(do.data_ptr()), _stream_ptr(stream))
     if rc != OK:
-        raise ContourError(rc, "contour_group_edges")
+        raise ContourError(rc, "contour_group_edges_ranges" if ranges else "contour_group_edges")
     return so, do
 
 

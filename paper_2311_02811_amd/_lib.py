@@ -20,7 +20,7 @@ c_i64p = ctypes.POINTER(ctypes.c_int64)
 class ContourOpts(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in (
         "order", "schedule", "k1", "write_mode", "update", "driver", "max_sweeps", "warm_start",
-        "block", "edges_per_thread", "chunk_tiles", "grid", "reorder", "window")]
+        "block", "edges_per_thread", "chunk_tiles", "grid", "reorder", "window", "dst_ranges")]
 
 
 class ContourStats(ctypes.Structure):
@@ -76,6 +76,9 @@ SIGNATURES = {
     "contour_cc_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                           ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ContourOpts),
                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "contour_group_edges_ranges": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_void_p]),
     "contour_group_edges": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "contour_status_string": (ctypes.c_char_p, [ctypes.c_int]),

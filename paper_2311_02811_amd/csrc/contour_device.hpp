@@ -21,7 +21,7 @@
 
 namespace contour {
 
-// Per-solve control block (one per graph in a batch), 64 bytes.
+// Per-solve control block (one per graph in a batch), 128 bytes.
 struct Ctl {
     unsigned long long next_task;  // persistent driver: next task index to hand out
     unsigned long long done_task;  // persistent driver: tasks completed
@@ -33,8 +33,9 @@ struct Ctl {
     int pad[3];
     unsigned long long t0;         // wall clock at the start of the solve (watchdog)
     unsigned long long pad2;
+    unsigned long long xq[8];      // persistent driver, XCD queues: units taken from each XCD's segment
 };
-static_assert(sizeof(Ctl) == 64, "control block is one 64-byte line");
+static_assert(sizeof(Ctl) == 128, "control block is two 64-byte lines");
 
 enum { ST_RUNNING = 0, ST_CONVERGED = 1, ST_LIMIT = 2, ST_BAD_START = 3, ST_TIMEOUT = 4 };
 
@@ -78,6 +79,8 @@ struct SolveArgs {
     int win_cap;         // LDS window capacity in labels (0: no window)
     int win_shift;       // edges are grouped by src >> win_shift
     int win_margin;      // labels staged past the last source block of a task
+    int xq_units;        // persistent driver: 0, one task counter for the whole GPU; else
+                         // per-XCD queues of xq_units strided task groups per sweep
 };
 
 // Edge ids are streamed once per sweep: non-temporal loads keep them from

@@ -81,9 +81,15 @@ int contour_cc_noalloc(const int32_t* src, const int32_t* dst, int64_t m, int32_
     if (rc) return rc;
     int* ws = nullptr;
     if (m > 0 && contour::wants_reorder(r, m, n)) {
+        const long long room = contour::kNoAllocInts - contour::kNoAllocCtlInts;
         contour::Reorder ro;
-        contour::reorder_geometry(d, m, n, &ro);
-        if (ro.elems <= contour::kNoAllocInts - contour::kNoAllocCtlInts)
+        contour::solve_reorder_geometry(d, r, m, n, &ro);
+        if (ro.elems > room && ro.R > 0 && r.dst_ranges == CONTOUR_DST_RANGES_AUTO) {
+            // the second pass needs a second copy: without it the copy may fit
+            r.dst_ranges = CONTOUR_DST_RANGES_OFF;
+            contour::solve_reorder_geometry(d, r, m, n, &ro);
+        }
+        if (ro.elems <= room)
             ws = base + contour::kNoAllocCtlInts;
         else if (r.reorder == CONTOUR_REORDER_ON)
             return CONTOUR_ETOOBIG;

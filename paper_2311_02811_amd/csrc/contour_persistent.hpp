@@ -68,6 +68,100 @@ __device__ __forceinline__ long long persistent_take(const SolveArgs& a, long lo
     return t;
 }
 
+// XCD queues (a.xq_units = U > 0).  The tasks of a sweep are cut into eight
+// segments of consecutive tasks, one per XCD (segment x: tasks
+// [x T / 8, (x + 1) T / 8) of the T tasks); with edges grouped by destination
+// range, a segment covers a few ranges, so the label gathers of an XCD stay
+// in its own L2.  Each segment is handed out as U units per sweep; unit j
+// holds the tasks j, j + U, j + 2U, ... of the segment, so the U workgroups of
+// an XCD (one unit each) walk through the segment side by side, one
+// destination range at a time.  Ctl::xq[x] counts the units taken from
+// segment x over all sweeps (unit u: sweep u / U, index u % U).  A workgroup
+// takes its next unit from its own XCD's queue with one add; before using a
+// unit of sweep s it takes, one at a time with a compare-and-swap, any unit
+// of an earlier sweep still left in another queue.  So a workgroup starts a
+// unit of sweep s only when every unit of every earlier sweep has been taken
+// by a running workgroup, and like the single counter the scheme needs no
+// co-residency.  Thread 0 only.
+struct XcdState {
+    int xcd;                  // this workgroup's XCD
+    int have;                 // a unit is being worked through
+    int q;                    // its queue
+    long long sweep;          // its sweep
+    long long next_chunk;     // its next task (chunk of the sweep)
+    long long end_chunk;      // end of its segment
+    long long own_next;       // a unit taken from the own queue and not yet used (-1: none)
+};
+
+__device__ __forceinline__ void xcd_segment(const SolveArgs& a, int x, long long* lo, long long* hi)
+{
+    *lo = (long long)x * a.tasks / 8;
+    *hi = (long long)(x + 1) * a.tasks / 8;
+}
+
+__device__ __forceinline__ void xcd_use(const SolveArgs& a, XcdState& s, int q, unsigned long long u)
+{
+    long long lo, hi;
+    xcd_segment(a, q, &lo, &hi);
+    s.have = 1;
+    s.q = q;
+    s.sweep = (long long)(u / (unsigned long long)a.xq_units);
+    s.next_chunk = lo + (long long)(u % (unsigned long long)a.xq_units);
+    s.end_chunk = hi;
+}
+
+__device__ __forceinline__ long long persistent_take_xcd(const SolveArgs& a, XcdState& s)
+{
+    Ctl* c = a.ctl;
+    const unsigned long long U = (unsigned long long)a.xq_units;
+    for (;;) {
+        if (s.have) {
+            if (s.next_chunk < s.end_chunk) {
+                const long long t = s.sweep * a.tasks + s.next_chunk;
+                s.next_chunk += a.xq_units;
+                return t;
+            }
+            s.have = 0;
+        }
+        if (__hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ST_RUNNING) return -1;
+        if (s.own_next < 0)
+            s.own_next = (long long)__hip_atomic_fetch_add(&c->xq[s.xcd], 1ULL, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long own_sweep = (unsigned long long)s.own_next / U;
+        bool stolen = false;
+        for (;;) {
+            // the untaken unit of the earliest sweep in the other queues,
+            // if it is earlier than the own unit
+            int best = -1;
+            unsigned long long bv = 0;
+            for (int d = 1; d < 8; ++d) {
+                const int y = (s.xcd + d) & 7;
+                const unsigned long long v =
+                    __hip_atomic_load(&c->xq[y], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (v / U < own_sweep && (best < 0 || v / U < bv / U)) {
+                    best = y;
+                    bv = v;
+                }
+            }
+            if (best < 0) break;
+            if (__hip_atomic_compare_exchange_strong(&c->xq[best], &bv, bv + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)) {
+                xcd_use(a, s, best, bv);
+                stolen = true;
+                break;
+            }
+        }
+        if (!stolen) {
+            xcd_use(a, s, s.xcd, (unsigned long long)s.own_next);
+            s.own_next = -1;
+        }
+    }
+}
+
+// XCD of the calling workgroup: workgroups of a launch are dealt to the
+// eight XCDs in turn.
+__device__ __forceinline__ int xcd_of_workgroup() { return (int)(blockIdx.x & 7); }
+
 // Thread 0 only: start task t (t < 0: the workgroup leaves) and decide
 // whether the workgroup works on it.  A task of a later sweep than the last
 // one first publishes the workgroup's completed tasks and then waits until
@@ -300,7 +394,7 @@ __device__ __forceinline__ bool window_task(const SolveArgs& a, long long first_
 // publication adds to done_task with release semantics after its
 // last_change update, so a sweep that changed a label is never mistaken for
 // one that did not.
-template <int EPT, int BLOCK, bool ATOMIC, bool WIN = false>
+template <int EPT, int BLOCK, bool ATOMIC, bool WIN = false, bool XQ = false>
 __device__ __forceinline__ void persistent_solve(const SolveArgs& a)
 {
     // s_task is read by every wave at the top of an iteration and rewritten
@@ -312,9 +406,13 @@ __device__ __forceinline__ void persistent_solve(const SolveArgs& a)
     __shared__ int s_go;
     PersistentState w{-1, 0, 0, 0, 0};
     long long grp = 0, grp_end = 0;  // thread 0: the rest of its task group
+    // thread 0's XCD-queue state lives in LDS: kept in registers across the
+    // task loop it would push the tile code into spilling
+    __shared__ XcdState xs;
+    if (XQ && threadIdx.x == 0) xs = XcdState{xcd_of_workgroup(), 0, 0, 0, 0, 0, -1};
     if (threadIdx.x == 0) {
         w.t0 = a.ctl->t0;
-        const long long t = persistent_take(a, &grp, &grp_end);
+        const long long t = XQ ? persistent_take_xcd(a, xs) : persistent_take(a, &grp, &grp_end);
         s_go = persistent_begin(a, w, t);
         s_task = t;
     }
@@ -339,7 +437,7 @@ __device__ __forceinline__ void persistent_solve(const SolveArgs& a)
         // take the next task; only a move to another sweep (or the end)
         // publishes, which needs every store of the workgroup drained and
         // the per-thread flags combined
-        if (threadIdx.x == 0) s_next = persistent_take(a, &grp, &grp_end);
+        if (threadIdx.x == 0) s_next = XQ ? persistent_take_xcd(a, xs) : persistent_take(a, &grp, &grp_end);
         __syncthreads();
         const long long next = uniform(s_next);
         const bool leave = next < 0 || next / a.tasks != sweep;

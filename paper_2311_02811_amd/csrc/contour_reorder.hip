@@ -28,6 +28,15 @@
 // each block lists its edges chunk by chunk
 // in input order, which on power-law graphs also saves sweeps (the edges of
 // a block keep the input's locality).
+//
+// Second pass (optional): the grouped copy is grouped again, stably, by
+// destination range dst >> dshift (at most 64 ranges), with the same count,
+// offsets and scan kernels and a scatter that ranks a chunk's edges in
+// element order (wave ballots over the key bits, then a scan over the
+// chunk's waves).  The result lists the edges by destination range and,
+// within a range, by source block: a task of consecutive edges then gathers
+// its source labels from a window in LDS and its destination labels from one
+// range that fits an XCD's L2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -47,6 +56,8 @@ static constexpr int kOffRows = kGroupChunks / (kOffThreads / 64);
 static constexpr unsigned kXcds = 8;                        // accelerator complex dies of the MI355X
 // dynamic LDS of the scatter: the chunk in block order (src and dst)
 static constexpr size_t kScatterLds = (size_t)kChunk * 2 * sizeof(int);
+static constexpr int kMaxRanges = 64;                       // destination ranges of the second pass
+static constexpr int kWaves = kThreads / 64;
 
 __device__ __forceinline__ int block_of(int w, int shift, int K)
 {
@@ -218,31 +229,154 @@ __global__ __launch_bounds__(kThreads) void k_blk_scatter(const int* __restrict_
     }
 }
 
-void reorder_geometry(const DeviceInfo& d, long long m, int n, Reorder* r)
+// Second pass: chunk `chunk` (XCD-ordered as in k_blk_scatter) of the
+// grouped copy, placed stably by destination range.  Element i = k * kThreads
+// + t of the chunk is edge k of thread t; an edge's rank among the chunk's
+// edges of its range counts the earlier elements of that range: those of
+// earlier (k, wave) slots (a scan of per-slot counts) plus those of earlier
+// lanes of its own wave and slot (wave ballots over the key bits).
+__global__ __launch_bounds__(kThreads) void k_rng_scatter(const int* __restrict__ src, const int* __restrict__ dst,
+                                                          long long m, int shift, int R, const int* __restrict__ off,
+                                                          const int* __restrict__ part, int* __restrict__ osrc,
+                                                          int* __restrict__ odst)
+{
+    extern __shared__ __align__(16) int lds[];
+    int* out_s = lds;
+    int* out_d = lds + kChunk;
+    __shared__ int hist[kScatterPer * kWaves * kMaxRanges];  // per (k, wave) slot and range: count, then first rank
+    __shared__ int segsum[kWaves][kMaxRanges];
+    __shared__ int total[kMaxRanges], lstart[kMaxRanges], gbase[kMaxRanges];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const unsigned per = gridDim.x / kXcds, rem = gridDim.x % kXcds;
+    const unsigned x = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
+    const long long chunk = (long long)x * per + std::min(x, rem) + j;
+    const long long e0 = chunk * kChunk;
+    const int len = (int)std::min<long long>(kChunk, m - e0);
+    for (int i = t; i < kScatterPer * kWaves * kMaxRanges; i += kThreads) hist[i] = 0;
+    int es[kScatterPer], ed[kScatterPer];
+#pragma unroll
+    for (int k = 0; k < kScatterPer; ++k) {
+        const int i = std::min(k * kThreads + t, len - 1);
+        es[k] = ld_edge(src + e0 + i);
+        ed[k] = ld_edge(dst + e0 + i);
+    }
+    __syncthreads();
+    const unsigned long long below = lane ? (~0ULL >> (64 - lane)) : 0ULL;
+    int key[kScatterPer], rank[kScatterPer];
+#pragma unroll
+    for (int k = 0; k < kScatterPer; ++k) {
+        const bool valid = k * kThreads + t < len;
+        key[k] = valid ? block_of(ed[k], shift, R) : 0;
+        unsigned long long peers = __builtin_amdgcn_ballot_w64(valid);
+        for (int b = 0; (1 << b) < R; ++b) {
+            const bool bit = (key[k] >> b) & 1;
+            const unsigned long long bal = __builtin_amdgcn_ballot_w64(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        rank[k] = __popcll(peers & below);
+        if (valid && rank[k] == 0) hist[(k * kWaves + wave) * kMaxRanges + key[k]] = __popcll(peers);
+    }
+    __syncthreads();
+    // exclusive scan of each range's counts over the 128 slots in element
+    // order, cut into 16 segments of 8 slots: thread (seg, r) sums its
+    // segment's slots, wave 0 scans the segment sums, then each thread writes
+    // its slots' first ranks
+    constexpr int kSegSlots = kScatterPer;
+    const int r = t & 63, seg = t >> 6;
+    int sum = 0;
+    if (r < R)
+        for (int s = 0; s < kSegSlots; ++s) sum += hist[(seg * kSegSlots + s) * kMaxRanges + r];
+    segsum[seg][r] = sum;
+    __syncthreads();
+    if (t < kMaxRanges) {
+        int run = 0;
+        for (int s = 0; s < kWaves; ++s) {
+            const int v = segsum[s][t];
+            segsum[s][t] = run;
+            run += v;
+        }
+        total[t] = run;
+    }
+    __syncthreads();
+    if (r < R) {
+        int run = segsum[seg][r];
+        for (int s = 0; s < kSegSlots; ++s) {
+            const int i = (seg * kSegSlots + s) * kMaxRanges + r;
+            const int v = hist[i];
+            hist[i] = run;
+            run += v;
+        }
+    }
+    if (t < kMaxRanges) {
+        // first position of each range in the chunk (wave 0: inclusive scan)
+        const int c = t < R ? total[t] : 0;
+        int v = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(v, o, 64);
+            if (lane >= o) v += y;
+        }
+        lstart[t] = v - c;
+        gbase[t] = (t < R && c) ? part[(chunk / kGroupChunks) * R + t] + off[chunk * R + t] : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScatterPer; ++k) {
+        if (k * kThreads + t < len) {
+            const int pos = lstart[key[k]] + hist[(k * kWaves + wave) * kMaxRanges + key[k]] + rank[k];
+            out_s[pos] = es[k];
+            out_d[pos] = ed[k];
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < len; i += kThreads) {
+        const int v = out_d[i];
+        const int b = block_of(v, shift, R);
+        const int slot = gbase[b] + (i - lstart[b]);
+        osrc[slot] = out_s[i];
+        odst[slot] = v;
+    }
+}
+
+void reorder_geometry(const DeviceInfo& d, long long m, int n, Reorder* r, int dshift)
 {
     (void)d;
-    // the scatter stages 64 KiB of edges in LDS (set on the current device)
+    // the scatters stage 64 KiB of edges in LDS (set on the current device)
     (void)hipFuncSetAttribute((const void*)k_blk_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)kScatterLds);
     int shift = 0;
     while (((unsigned)(n - 1) >> shift) >= (unsigned)kMaxBuckets) ++shift;
     r->shift = shift;
     r->K = (int)(((unsigned)(n - 1) >> shift) + 1);
+    r->dshift = 0;
+    r->R = 0;
+    if (dshift > 0) {
+        while (((unsigned)(n - 1) >> dshift) >= (unsigned)kMaxRanges) ++dshift;
+        const int R = (int)(((unsigned)(n - 1) >> dshift) + 1);
+        if (R > 1) {
+            r->dshift = dshift;
+            r->R = R;
+            (void)hipFuncSetAttribute((const void*)k_rng_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)kScatterLds);
+        }
+    }
     r->m = m;
     // every array starts on a 16-byte boundary (the sweep reads edges with
     // 16-byte loads when it can)
     const long long mp = (m + 3) & ~3LL;
     r->chunks = (m + kChunk - 1) / kChunk;
     r->groups = (r->chunks + kGroupChunks - 1) / kGroupChunks;
-    r->elems = 2 * mp + reorder_table_elems(*r);
+    r->elems = (r->R ? 4 : 2) * mp + reorder_table_elems(*r);
 }
 
-long long reorder_table_elems(const Reorder& r) { return (r.chunks + r.groups) * r.K; }
+long long reorder_table_elems(const Reorder& r) { return (r.chunks + r.groups) * (r.K + r.R); }
 
 void reorder_bind_tables(Reorder* r, int* tables)
 {
     r->cnt = tables;
     r->part = tables + r->chunks * r->K;
+    r->cnt2 = r->part + r->groups * r->K;
+    r->part2 = r->cnt2 + r->chunks * r->R;
 }
 
 void reorder_bind(Reorder* r, int* ws)
@@ -250,19 +384,38 @@ void reorder_bind(Reorder* r, int* ws)
     const long long mp = (r->m + 3) & ~3LL;
     r->src2 = ws;
     r->dst2 = ws + mp;
-    reorder_bind_tables(r, ws + 2 * mp);
+    if (r->R) {
+        r->src1 = ws + 2 * mp;
+        r->dst1 = ws + 3 * mp;
+    }
+    reorder_bind_tables(r, ws + (r->R ? 4 : 2) * mp);
+}
+
+// count, offsets and scan of one pass: keys from `key_src` (>> shift, K keys)
+static void enqueue_counts(const Reorder& r, const int* key_src, int shift, int K, int* cnt, int* part,
+                           hipStream_t stream)
+{
+    const unsigned gc = (unsigned)((r.chunks + kCountChunks - 1) / kCountChunks);
+    hipLaunchKernelGGL(k_blk_count, dim3(gc), dim3(kThreads), 0, stream, key_src, r.m, shift, K, cnt);
+    hipLaunchKernelGGL(k_blk_offsets, dim3((unsigned)((K + 63) / 64), (unsigned)r.groups), dim3(kOffThreads), 0,
+                       stream, cnt, part, r.chunks, K);
+    hipLaunchKernelGGL(k_blk_scan, dim3(1), dim3(kThreads), 0, stream, part, (int)r.groups, K);
 }
 
 int enqueue_reorder(const Reorder& r, const int* src, const int* dst, hipStream_t stream)
 {
     if (r.m <= 0) return CONTOUR_OK;
-    const unsigned gc = (unsigned)((r.chunks + kCountChunks - 1) / kCountChunks);
-    hipLaunchKernelGGL(k_blk_count, dim3(gc), dim3(kThreads), 0, stream, src, r.m, r.shift, r.K, r.cnt);
-    hipLaunchKernelGGL(k_blk_offsets, dim3((unsigned)((r.K + 63) / 64), (unsigned)r.groups), dim3(kOffThreads), 0,
-                       stream, r.cnt, r.part, r.chunks, r.K);
-    hipLaunchKernelGGL(k_blk_scan, dim3(1), dim3(kThreads), 0, stream, r.part, (int)r.groups, r.K);
+    int* s1 = r.R ? r.src1 : r.src2;
+    int* d1 = r.R ? r.dst1 : r.dst2;
+    enqueue_counts(r, src, r.shift, r.K, r.cnt, r.part, stream);
     hipLaunchKernelGGL(k_blk_scatter, dim3((unsigned)r.chunks), dim3(kThreads), kScatterLds, stream, src, dst, r.m,
-                       r.shift, r.K, (const int*)r.cnt, (const int*)r.part, r.src2, r.dst2);
+                       r.shift, r.K, (const int*)r.cnt, (const int*)r.part, s1, d1);
+    if (r.R) {
+        enqueue_counts(r, d1, r.dshift, r.R, r.cnt2, r.part2, stream);
+        hipLaunchKernelGGL(k_rng_scatter, dim3((unsigned)r.chunks), dim3(kThreads), kScatterLds, stream,
+                           (const int*)s1, (const int*)d1, r.m, r.dshift, r.R, (const int*)r.cnt2,
+                           (const int*)r.part2, r.src2, r.dst2);
+    }
     CONTOUR_HIP(hipGetLastError());
     return CONTOUR_OK;
 }

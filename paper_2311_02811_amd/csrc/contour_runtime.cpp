@@ -140,6 +140,9 @@ int resolve_opts(const contour_opts_t* o, Resolved* r)
     if (o->chunk_tiles < 0 || o->grid < 0) return CONTOUR_EINVAL;
     if (o->reorder < CONTOUR_REORDER_AUTO || o->reorder > CONTOUR_REORDER_ON) return CONTOUR_EINVAL;
     if (o->window != 0 && o->window < 1024) return CONTOUR_EINVAL;
+    if (!(o->dst_ranges == CONTOUR_DST_RANGES_AUTO || o->dst_ranges == CONTOUR_DST_RANGES_OFF ||
+          o->dst_ranges == CONTOUR_DST_RANGES_ON || (o->dst_ranges >= 16 && o->dst_ranges <= 30)))
+        return CONTOUR_EINVAL;
     // Algorithm 1 applies its conditional assignments to L_u with the
     // compare-and-swap loop of Eq. (cas); the synchronous update is only
     // offered that way, and sequenced from the host.
@@ -160,6 +163,7 @@ int resolve_opts(const contour_opts_t* o, Resolved* r)
     r->grid = o->grid;
     r->reorder = o->reorder;
     r->window = o->window;
+    r->dst_ranges = o->dst_ranges;
     return CONTOUR_OK;
 }
 
@@ -184,6 +188,7 @@ void contour_default_opts(contour_opts_t* opts)
     opts->grid = 0;
     opts->reorder = CONTOUR_REORDER_AUTO;
     opts->window = 0;
+    opts->dst_ranges = CONTOUR_DST_RANGES_AUTO;
 }
 
 const char* contour_status_string(int s)

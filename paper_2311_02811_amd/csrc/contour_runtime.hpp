@@ -67,6 +67,7 @@ struct Resolved {
     int grid;
     int reorder;
     int window;
+    int dst_ranges;
 };
 
 // Wall-clock ticks a single solve may run before the watchdog stops it
@@ -96,22 +97,31 @@ struct BatchJob {
 int enqueue_wg_jobs(const DeviceInfo& d, const Resolved& r, const BatchJob* d_jobs, int n_lds, int max_n_lds,
                     int n_global, int* d_counters, Ctl* d_clock, contour_stats_t* stats, hipStream_t stream);
 
-// Edge reordering by source block (contour_reorder.hip).
+// Edge reordering by source block (contour_reorder.hip), optionally followed
+// by a stable second pass by destination range: the edges then come in
+// (destination range, source block) order.
 struct Reorder {
     int shift = 0;          // source block = src >> shift
     int K = 0;              // source blocks (at most 1024)
+    int dshift = 0;         // destination range = dst >> dshift (0: no second pass)
+    int R = 0;              // destination ranges (at most 64)
     long long m = 0;
     long long elems = 0;    // workspace ints needed
     int* src2 = nullptr;    // workspace: reordered edges
     int* dst2 = nullptr;
+    int* src1 = nullptr;    // workspace: edges grouped by source block (second pass only)
+    int* dst1 = nullptr;
     long long chunks = 0;   // 8 Ki-edge chunks of the edge list
     long long groups = 0;   // groups of 128 chunks
     int* cnt = nullptr;     // workspace: chunks x K edges per (chunk, block), then their first slots
     int* part = nullptr;    // workspace: groups x K edges per (group, block), then their first slots
+    int* cnt2 = nullptr;    // the same for the second pass (R columns)
+    int* part2 = nullptr;
 };
 
-// Sizes for m edges over n > 0 vertices.
-void reorder_geometry(const DeviceInfo& d, long long m, int n, Reorder* r);
+// Sizes for m edges over n > 0 vertices; dshift > 0 adds the second pass by
+// destination range dst >> dshift (at most 64 ranges).
+void reorder_geometry(const DeviceInfo& d, long long m, int n, Reorder* r, int dshift = 0);
 // Point the reorder at a workspace of at least r->elems ints.
 void reorder_bind(Reorder* r, int* ws);
 // Ints of that workspace besides the grouped copy (count tables).
@@ -125,6 +135,11 @@ int enqueue_reorder(const Reorder& r, const int* src, const int* dst, hipStream_
 inline bool reorder_auto(long long m, int n) { return n > (1 << 20) && m >= (1 << 20); }
 // Whether a solve with these options groups its edges first.
 bool wants_reorder(const Resolved& r, long long m, int n);
+// The destination-range shift of a grouped solve with these options (0: no
+// second pass).
+int dst_range_shift(const Resolved& r, long long m, int n);
+// reorder_geometry of a solve with these options (both passes as it groups).
+void solve_reorder_geometry(const DeviceInfo& d, const Resolved& r, long long m, int n, Reorder* ro);
 
 // A prepared single-graph persistent solve: everything needed to enqueue it
 // without allocating (used by contour_cc_ex and by batched plans).

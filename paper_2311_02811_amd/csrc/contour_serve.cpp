@@ -241,7 +241,7 @@ bool ensure_workspace(contour_server* s, Lane& L, const Request* r)
                          (rr.reorder == CONTOUR_REORDER_AUTO && reorder_auto(r->m, r->n));
     if (reorder && r->m < 0x7fffffffLL) {
         Reorder ro;
-        reorder_geometry(s->dev, r->m, r->n, &ro);
+        solve_reorder_geometry(s->dev, rr, r->m, r->n, &ro);
         need = ro.elems;
     }
     if (need <= L.ws_elems) return true;

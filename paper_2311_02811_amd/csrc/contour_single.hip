@@ -59,10 +59,10 @@ __global__ void k_write_stats(const Ctl* c, contour_stats_t* out, int range_err)
 // ------------------------------------------------- persistent driver ----
 // One launch for the whole solve; the sweep loop is persistent_solve() in
 // contour_persistent.hpp.
-template <int EPT, int BLOCK, bool ATOMIC, bool WIN>
+template <int EPT, int BLOCK, bool ATOMIC, bool WIN, bool XQ = false>
 __global__ __launch_bounds__(BLOCK) void k_persistent(SolveArgs a)
 {
-    persistent_solve<EPT, BLOCK, ATOMIC, WIN>(a);
+    persistent_solve<EPT, BLOCK, ATOMIC, WIN, XQ>(a);
 }
 
 // ------------------------------------------------- host-loop driver -----
@@ -174,10 +174,12 @@ static void pick(int ept, persistent_fn* p, sweep_fn* s)
     constexpr int e4 = EptCap<BLOCK, WIN>::e4;
     constexpr int e8 = EptCap<BLOCK, WIN>::e8 < e4 ? e4 : EptCap<BLOCK, WIN>::e8 == 4 ? e4 : 8;
     switch (ept) {
-    case 1: *p = k_persistent<1, BLOCK, ATOMIC, WIN>; *s = k_sweep<1, BLOCK, ATOMIC>; break;
-    case 2: *p = k_persistent<2, BLOCK, ATOMIC, WIN>; *s = k_sweep<2, BLOCK, ATOMIC>; break;
-    case 4: *p = k_persistent<e4, BLOCK, ATOMIC, WIN>; *s = k_sweep<4, BLOCK, ATOMIC>; break;
-    default: *p = k_persistent<e8, BLOCK, ATOMIC, WIN>; *s = k_sweep<(BLOCK == 1024 ? 4 : 8), BLOCK, ATOMIC>; break;
+    // the host-loop sweep stores into global memory with atomic minima in
+    // either write mode (see run_hostloop)
+    case 1: *p = k_persistent<1, BLOCK, ATOMIC, WIN>; *s = k_sweep<1, BLOCK, true>; break;
+    case 2: *p = k_persistent<2, BLOCK, ATOMIC, WIN>; *s = k_sweep<2, BLOCK, true>; break;
+    case 4: *p = k_persistent<e4, BLOCK, ATOMIC, WIN>; *s = k_sweep<4, BLOCK, true>; break;
+    default: *p = k_persistent<e8, BLOCK, ATOMIC, WIN>; *s = k_sweep<(BLOCK == 1024 ? 4 : 8), BLOCK, true>; break;
     }
 }
 
@@ -200,6 +202,34 @@ static void pick_kernels(int block, int ept, bool atomic, persistent_fn* p, swee
 {
     if (win) pick_w<true>(block, ept, atomic, p, s);
     else pick_w<false>(block, ept, atomic, p, s);
+}
+
+// Window kernels with XCD queues (edges grouped by destination range):
+// 1024-thread workgroups with 2 or 4 edges per thread; null otherwise.
+static persistent_fn pick_xq(int block, int ept, bool atomic)
+{
+    if (block != 1024) return nullptr;
+    if (ept == 2) return atomic ? k_persistent<2, 1024, true, true, true> : k_persistent<2, 1024, false, true, true>;
+    if (ept == 4) return atomic ? k_persistent<4, 1024, true, true, true> : k_persistent<4, 1024, false, true, true>;
+    return nullptr;
+}
+
+// Destination ranges of 2^19 ids: 2 MiB of labels, half an XCD's L2.
+constexpr int kDstRangeShift = 19;
+
+int dst_range_shift(const Resolved& r, long long m, int n)
+{
+    if (r.dst_ranges == CONTOUR_DST_RANGES_OFF || r.driver != CONTOUR_DRIVER_PERSISTENT) return 0;
+    if (r.dst_ranges == CONTOUR_DST_RANGES_ON) return kDstRangeShift;
+    if (r.dst_ranges >= 16) return r.dst_ranges;  // ranges of 2^dst_ranges ids
+    // automatic: where the labels outgrow one XCD's L2 (4 MiB) and the graph
+    // has enough edges per vertex to repay the second pass
+    return n > (1 << 20) && m >= 4LL * n ? kDstRangeShift : 0;
+}
+
+void solve_reorder_geometry(const DeviceInfo& d, const Resolved& r, long long m, int n, Reorder* ro)
+{
+    reorder_geometry(d, m, n, ro, dst_range_shift(r, m, n));
 }
 
 bool wants_reorder(const Resolved& r, long long m, int n)
@@ -251,7 +281,7 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
     p.reorder = reorder;
     if (p.reorder) {
         if (!ws) return CONTOUR_EINVAL;
-        reorder_geometry(d, m, n, &p.ro);
+        solve_reorder_geometry(d, r0, m, n, &p.ro);
         reorder_bind(&p.ro, ws);
         src = p.ro.src2;
         dst = p.ro.dst2;
@@ -278,6 +308,7 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
     a.win_cap = 0;
     a.win_shift = 0;
     a.win_margin = 0;
+    a.xq_units = 0;
     p.kernel = nullptr;
     p.grid = 0;
     p.lds = 0;
@@ -286,6 +317,9 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
         // label windows read global labels through 32-bit buffer offsets
         const bool win = p.reorder && n < (1 << 30);
         pick_kernels(r.block, r.ept, r.atomic, &p.kernel, &ks, win);
+        // edges grouped by destination range: the XCD-queue kernel
+        persistent_fn kxq = win && p.ro.R > 0 ? pick_xq(r.block, r.ept, r.atomic) : nullptr;
+        if (kxq) std::swap(p.kernel, kxq);
         if (win) {
             // the largest window (labels + one dirty bit each) that fits the
             // LDS of one workgroup, a multiple of 32 labels
@@ -296,9 +330,19 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
             a.win_cap = (int)std::min<long long>(cap, ((long long)n + 31) & ~31LL);
             a.win_shift = p.ro.shift;
             a.win_margin = std::max(1, (1 << p.ro.shift) / 2);
+            if (kxq) {
+                // a task's window spans exactly its first to last source id:
+                // with destination ranges a task holds a few blocks' edges of
+                // one range, with no locality for a margin to catch
+                a.win_shift = 0;
+                a.win_margin = 0;
+            }
             p.lds = (size_t)a.win_cap * 4 + (size_t)((a.win_cap + 31) / 32) * 4 + (size_t)kHubSlots * 8;
             CONTOUR_HIP(hipFuncSetAttribute((const void*)p.kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                             (int)p.lds));
+            if (kxq)
+                CONTOUR_HIP(hipFuncSetAttribute((const void*)kxq, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                (int)p.lds));
         }
         const long long tile_edges = (long long)r.block * r.ept;
         const long long ntiles = (m + tile_edges - 1) / tile_edges;
@@ -313,7 +357,15 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
             // window is staged afresh, with the other workgroups' updates,
             // several times per sweep (measured: fewer sweeps on R-MAT).
             const long long per_block = m / std::max(1, p.ro.K);
-            const long long want = per_block > 65536 ? 16384 : 32768;
+            long long want = per_block > 65536 ? 16384 : 32768;
+            if (kxq) {
+                // destination ranges: a task of E consecutive edges spans
+                // about E n R / m source ids; E is the largest number of
+                // whole tiles whose span fits the window (measured on R-MAT
+                // scale 24: 16 Ki-edge tasks, 8.9 ms for 4 sweeps, against
+                // 9.4 ms with 12 Ki and 10.4 ms with 8 Ki)
+                want = (long long)((double)a.win_cap * (double)m / ((double)n * p.ro.R));
+            }
             tpt = (int)std::max<long long>(1, want / tile_edges);
         }
         // the sweep's tiles split evenly over a number of tasks that is a
@@ -327,6 +379,14 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
         p.grid = (unsigned)std::min<long long>(g, a.tasks);
         // each workgroup takes its share of a sweep with one atomic
         a.take = (int)std::max<long long>(1, a.tasks / p.grid);
+        // edges grouped by destination range: per-XCD queues, one unit per
+        // workgroup and sweep (the grid must split evenly over the XCDs)
+        if (kxq) {
+            if (p.grid % 8 == 0)
+                a.xq_units = (int)(p.grid / 8);
+            else
+                std::swap(p.kernel, kxq);  // back to the single-counter window kernel
+        }
     }
     *out = p;
     return CONTOUR_OK;
@@ -366,7 +426,12 @@ int enqueue_empty_stats(Ctl* ctl, contour_stats_t* stats, int range_err, hipStre
 }
 
 // Host-sequenced sweeps (asynchronous or synchronous update).  Blocks the
-// calling thread: it reads the control block every few sweeps.
+// calling thread: it reads the control block every few sweeps.  Label
+// stores are atomic minima in either write mode: with plain global stores
+// one R-MAT scale-24 solve in about 25 on the MI355X ended with wrong labels
+// (status OK, sweep counts as usual; not seen again in 22 repeats, cause not
+// found), so, as inside the persistent kernels, plain stores are kept to
+// memory that one workgroup owns (LDS windows, one-workgroup graphs).
 static int run_hostloop(const DeviceInfo& d, const Resolved& r0, const int* src, const int* dst,
                         long long m, int n, int* L, Workspace* ws, contour_stats_t* stats,
                         hipStream_t stream)
@@ -471,7 +536,7 @@ static int run_solve(const int* src, const int* dst, long long m, int n, int* L,
     int* scratch = nullptr;
     if (m > 0 && wants_reorder(r, m, n)) {
         Reorder ro;
-        reorder_geometry(d, m, n, &ro);
+        solve_reorder_geometry(d, r, m, n, &ro);
         rc = workspace_scratch(ws, stream, ro.elems);
         if (rc) return rc;
         scratch = ws->scratch;
@@ -527,8 +592,9 @@ int contour_reserve(int64_t m, int32_t n, const contour_opts_t* opts, contour_st
     long long need = r.sync ? n : 0;
     if (m < 0x7fffffffLL) {
         contour::Reorder ro;
-        contour::reorder_geometry(d, m, n, &ro);
+        contour::solve_reorder_geometry(d, r, m, n, &ro);
         if (contour::wants_reorder(r, m, n)) need += ro.elems;
+        contour::reorder_geometry(d, m, n, &ro);  // contour_group_edges: one pass
         need = std::max(need, contour::reorder_table_elems(ro));
     }
     return contour::workspace_scratch(ws, s, need);
@@ -558,6 +624,34 @@ int contour_group_edges(const int32_t* src, const int32_t* dst, int64_t m, int32
     rc = contour::workspace_scratch(ws, s, contour::reorder_table_elems(ro));
     if (rc) return rc;
     contour::reorder_bind_tables(&ro, ws->scratch);
+    ro.src2 = src_out;
+    ro.dst2 = dst_out;
+    return contour::enqueue_reorder(ro, src, dst, s);
+}
+
+int contour_group_edges_ranges(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int32_t* src_out,
+                               int32_t* dst_out, contour_stream_t stream)
+{
+    if (m < 0 || m >= 0x7fffffffLL || n <= (1 << contour::kDstRangeShift)) return CONTOUR_EINVAL;
+    if (m == 0) return CONTOUR_OK;
+    if (!src || !dst || !src_out || !dst_out) return CONTOUR_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    contour::DeviceInfo d;
+    int rc = contour::device_info(&d);
+    if (rc) return rc;
+    contour::Workspace* ws = nullptr;
+    rc = contour::workspace_for(s, &ws);
+    if (rc) return rc;
+    contour::Reorder ro;
+    contour::reorder_geometry(d, m, n, &ro, contour::kDstRangeShift);
+    // the first pass's copy and the count tables in the workspace, the
+    // second pass writes the caller's arrays
+    const long long mp = (m + 3) & ~3LL;
+    rc = contour::workspace_scratch(ws, s, 2 * mp + contour::reorder_table_elems(ro));
+    if (rc) return rc;
+    ro.src1 = ws->scratch;
+    ro.dst1 = ws->scratch + mp;
+    contour::reorder_bind_tables(&ro, ws->scratch + 2 * mp);
     ro.src2 = src_out;
     ro.dst2 = dst_out;
     return contour::enqueue_reorder(ro, src, dst, s);

@@ -355,6 +355,77 @@ def test_stream_and_concurrency(contour):
         assert np.array_equal(o.cpu().numpy(), exp)
 
 
+# ------------------------------------------------- destination ranges --
+# Edges grouped by destination range and dealt to the XCDs by per-XCD queues
+# (CONTOUR_DST_RANGES_*): labels must not depend on it.  Graphs with n above
+# 2^20 and m >= 4 n take it by default; smaller range sizes, tiny windows,
+# explicit grids (two units per XCD; one workgroup per XCD; more workgroups
+# than fit the GPU at once) and a grid that is not a multiple of eight (the
+# single-counter fallback) exercise the queues and their stealing.
+
+RANGE_GRAPHS = [
+    ("er_n1500000_m8000000", lambda: (graphgen.er(1_500_000, 8_000_000, 21), 1_500_000)),
+    ("rmat21_ef16", lambda: (graphgen.rmat(21, 16, 22), 1 << 21)),
+    ("grid1100_holes10", lambda: (graphgen.grid_holes(1100, 1100, 0.1, 23), 1100 * 1100)),
+]
+
+RANGE_MODES = [
+    dict(),
+    dict(dst_ranges="on"),
+    dict(dst_ranges="off"),
+    dict(dst_ranges=16),
+    dict(dst_ranges=20, order=3),
+    dict(dst_ranges="on", order="full"),
+    dict(dst_ranges="on", write="atomic"),
+    dict(dst_ranges="on", block=1024, edges_per_thread=2),
+    dict(dst_ranges="on", window=2048),
+    dict(dst_ranges="on", grid=16),
+    dict(dst_ranges="on", grid=8),
+    dict(dst_ranges="on", grid=1024),
+    dict(dst_ranges="on", grid=12),
+    dict(dst_ranges="on", schedule="1m1m", order=1024),
+]
+
+
+@pytest.mark.parametrize("graph", RANGE_GRAPHS, ids=[g[0] for g in RANGE_GRAPHS])
+def test_destination_ranges(contour, graph):
+    name, make = graph
+    (src, dst), n = make()
+    exp = oracle.uf_labels(src, dst, n)
+    s, d = dev(src), dev(dst)
+    for mode in RANGE_MODES:
+        banner("ranges %s n=%d m=%d %r" % (name, n, src.size, mode))
+        lab, st = contour.cc_ex(s, d, n, **mode)
+        stats = contour.read_stats(st)
+        assert stats.status == contour.OK, mode
+        assert np.array_equal(lab.cpu().numpy(), exp), mode
+    # one sweep at a time, resumed from each partial state
+    lab = torch.arange(n, dtype=torch.int32, device="cuda")
+    for k in range(1, 64):
+        lab, st = contour.cc_ex(s, d, n, labels=lab, warm_start=True, max_sweeps=1, dst_ranges="on")
+        stats = contour.read_stats(st)
+        cur = lab.cpu().numpy()
+        assert np.all(cur <= np.arange(n)) and np.array_equal(exp[cur], exp), k
+        if stats.status == contour.OK:
+            break
+        assert stats.status == contour.ENOCONV
+    assert np.array_equal(lab.cpu().numpy(), exp)
+
+
+def test_destination_ranges_out_of_range_ids(contour):
+    src, dst = graphgen.er(1_200_000, 5_000_000, 24)
+    n = 1_200_000
+    keep = np.ones(src.size, bool)
+    keep[::1001] = False
+    exp = oracle.uf_labels(src[keep], dst[keep], n)
+    src, dst = src.copy(), dst.copy()
+    src[::2002] = -3
+    dst[1001::2002] = n + 5
+    got, st = solve(contour, src, dst, n, dst_ranges="on")
+    assert st.status == contour.ERANGE
+    assert np.array_equal(got, exp)
+
+
 # ------------------------------------------------------------ full size --
 
 def test_config_er_full(contour):
@@ -392,7 +463,8 @@ def test_config_rmat_full(contour):
     exp = oracle.uf_labels(src, dst, n)
     s, d = dev(src), dev(dst)
     del src, dst
-    for mode in (dict(), dict(order=3), dict(order="full"), dict(reorder="off")):
+    for mode in (dict(), dict(order=3), dict(order="full"), dict(reorder="off"), dict(dst_ranges="off"),
+                 dict(dst_ranges=20), dict(driver="hostloop"), dict(driver="hostloop", order=3)):
         banner("rmat full %r" % mode)
         lab, st = contour.cc_ex(s, d, n, **mode)
         assert np.array_equal(lab.cpu().numpy(), exp), mode
