@@ -155,8 +155,9 @@ typedef struct {
     int32_t reserved;
 } contour_stats_t;
 
-/* Fill *opts with the defaults (order 2, fixed schedule, plain writes,
- * asynchronous update, persistent driver, no sweep limit, automatic geometry). */
+/* Fill *opts with the defaults (order 0, i.e. 2 for a solve and the tuned
+ * order in a batched plan; fixed schedule, plain writes, asynchronous update,
+ * persistent driver, no sweep limit, automatic geometry). */
 void contour_default_opts(contour_opts_t* opts);
 
 /* contour_cc: labels_out[v] = minimum vertex id of v's component.
@@ -323,9 +324,13 @@ typedef struct {
 
 /* Build a reusable plan: sorts the graphs into size classes (labels in LDS,
  * one workgroup per graph with labels in global memory, several workgroups
- * per graph), picks the per-class order and geometry (opts fields that are
- * non-zero override the tuned choice), and allocates the plan's device
- * tables.  The pointers in *batch are captured; the arrays they point to
+ * per graph), picks the per-class order and geometry, and allocates the
+ * plan's device tables.  Non-zero opts->order, opts->block and
+ * opts->edges_per_thread override the tuned choice for every class where the
+ * value is allowed (block 1024 for classes 0 and 1, 8 edges per thread for
+ * class 2); zero fields take the tuning table's choice, else the defaults.
+ * opts->chunk_tiles, grid, reorder, window and dst_ranges do not apply to
+ * plans.  The pointers in *batch are captured; the arrays they point to
  * must stay valid for launches.  Returns CONTOUR_OK, CONTOUR_EINVAL,
  * CONTOUR_ENOMEM or CONTOUR_EHIP. */
 int contour_batch_plan_create(const contour_batch_t* batch, const contour_opts_t* opts,

@@ -70,7 +70,7 @@ def _check_edges(src, dst):
         raise ValueError("src and dst are on different devices")
 
 
-def make_opts(order=2, schedule="fixed", k1=2, write="plain", update="async",
+def make_opts(order=0, schedule="fixed", k1=2, write="plain", update="async",
               driver="persistent", max_sweeps=0, warm_start=False, block=0,
               edges_per_thread=0, chunk_tiles=0, grid=0, reorder="auto", window=0,
               dst_ranges="auto") -> ContourOpts:

@@ -431,6 +431,12 @@ static int create_plan(const contour_batch_t* b, const contour_opts_t* opts, con
     for (int c = 0; c < 3; ++c) {
         rc = class_geometry(t, c, &block[c], &ept[c], &order[c], r.sched.order);
         if (rc) return rc;
+        // explicit (non-zero) options override the tuned choice, for every
+        // class where the value is allowed
+        if (opts && opts->order != 0) order[c] = r.sched.order;
+        if (opts && opts->block != 0 && (opts->block != 1024 || c < 2)) block[c] = opts->block;
+        if (opts && opts->edges_per_thread != 0 && (opts->edges_per_thread != 8 || c == 2))
+            ept[c] = opts->edges_per_thread;
     }
 
     contour_plan* p = new (std::nothrow) contour_plan();

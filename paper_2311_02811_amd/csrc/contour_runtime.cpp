@@ -174,7 +174,7 @@ extern "C" {
 void contour_default_opts(contour_opts_t* opts)
 {
     if (!opts) return;
-    opts->order = 2;
+    opts->order = 0;  // the default order: 2 for a solve, the tuned order in a batched plan
     opts->schedule = CONTOUR_SCHED_FIXED;
     opts->k1 = 2;
     opts->write_mode = CONTOUR_WRITE_PLAIN;

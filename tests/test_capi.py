@@ -42,7 +42,7 @@ def test_host_only_calls_work_without_gpu():
     assert lib.contour_status_string(0) == b"ok"
     assert lib.contour_status_string(2).startswith(b"edge id")
     o = contour.make_opts()
-    assert o.order == 2 and o.write_mode == 0 and o.driver == 0
+    assert o.order == 0 and o.write_mode == 0 and o.driver == 0   # 0: the default order
     assert contour.make_opts(order="full").order == -1
     assert b"gfx950" in lib.contour_version()
 

@@ -307,3 +307,29 @@ def test_class1_window_out_of_range_ids(contour):
     assert classes == [0, 1, 0]
     assert stats[0, 0] == contour.ERANGE
     assert np.array_equal(labels, exp)
+
+
+def test_explicit_options_override_the_tuning(contour):
+    # Non-zero opts fields take precedence over the tuning table.  Paths with
+    # increasing ids: order 1 needs many more sweeps than order 2, so the
+    # sweep counts show which order the plan ran.
+    n, G = 3000, 3
+    src = np.concatenate([np.arange(n - 1, dtype=np.int32)] * G)
+    dst = src + 1
+    eo = np.arange(G + 1, dtype=np.int64) * (n - 1)
+    vo = np.arange(G + 1, dtype=np.int64) * n
+    exp = oracle.uf_batch(eo, vo, src, dst)
+    s, d = dev(src), dev(dst)
+    tuning = contour.make_tuning([dict(order=2)] * 3)
+    sweeps = {}
+    for key, opts in (("tuned", dict()), ("explicit", dict(order=1)), ("explicit_block", dict(order=1, block=256))):
+        banner("plan with tuning order 2, opts %r" % opts)
+        plan = contour.BatchPlan(eo, vo, s, d, tuning=tuning, **opts)
+        plan.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(plan.labels.cpu().numpy(), exp), key
+        sweeps[key] = int(plan.stats[:, 1].max().item())
+        plan.close()
+    print("sweeps", sweeps)
+    assert sweeps["explicit"] > 3 * sweeps["tuned"]
+    assert sweeps["explicit_block"] > 3 * sweeps["tuned"]

@@ -378,6 +378,7 @@ RANGE_MODES = [
     dict(dst_ranges="on", order="full"),
     dict(dst_ranges="on", write="atomic"),
     dict(dst_ranges="on", block=1024, edges_per_thread=2),
+    dict(dst_ranges="on", block=1024, edges_per_thread=4),
     dict(dst_ranges="on", window=2048),
     dict(dst_ranges="on", grid=16),
     dict(dst_ranges="on", grid=8),

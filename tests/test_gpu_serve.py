@@ -119,3 +119,58 @@ def test_serving_edge_cases(contour):
     assert np.array_equal(outs[2].numpy(), [0, 1, 2])
     assert results[ids[3]]["status"] == contour.ERANGE
     assert np.array_equal(outs[3].numpy(), [0, 0, 2, 3])
+
+
+def test_serving_config5_trace_with_rmat22_matches_oracle(contour):
+    # The serving workload's shape at full request size: Poisson arrivals at
+    # 2000/s drawn from the batch distribution plus 1% R-MAT scale-22 graphs
+    # (n = 4,194,304, m = 67,108,864) from a pool of two; one second of the
+    # trace, paced, then the same requests all at once.  Every request is
+    # compared with the oracle's labels of its pool item.
+    b = graphgen.batch(2000, 11)
+    small_exact = oracle.uf_batch(b.edge_off, b.vertex_off, b.src, b.dst)
+    pool = []
+    for k in range(2):
+        s2, d2 = graphgen.rmat(22, 16, 500 + k)
+        pool.append((pinned(s2), pinned(d2), 1 << 22, oracle.uf_labels(s2, d2, 1 << 22)))
+    src_p, dst_p = pinned(b.src), pinned(b.dst)
+    count = 2000
+    t_arr, big, pick = graphgen.poisson_trace(count, 2000.0, 0.01, b.num_graphs, len(pool), 11)
+    assert 5 <= int(big.sum()) <= 60
+
+    def req(i):
+        if big[i]:
+            s, d, n, exp = pool[int(pick[i])]
+            return s, d, n, exp
+        g = int(pick[i])
+        a, z = int(b.edge_off[g]), int(b.edge_off[g + 1])
+        v0, v1 = int(b.vertex_off[g]), int(b.vertex_off[g + 1])
+        return src_p[a:z], dst_p[a:z], v1 - v0, small_exact[v0:v1]
+
+    for paced in (True, False):
+        print("config-5 trace: %d requests (%d R-MAT-22), paced=%s" % (count, int(big.sum()), paced), flush=True)
+        srv = contour.Server(lanes=4)
+        outs, ids = [], []
+        t0 = time.perf_counter()
+        for i in range(count):
+            if paced:
+                while time.perf_counter() < t0 + t_arr[i]:
+                    pass
+            s, d, n, _ = req(i)
+            lab = torch.full((max(n, 1),), -7, dtype=torch.int32).pin_memory()
+            ids.append(srv.submit(s, d, n, lab))
+            outs.append(lab)
+        srv.drain()
+        results = {}
+        while True:
+            got = srv.poll(4096)
+            if not got:
+                break
+            for r in got:
+                results[r["id"]] = r
+        srv.close()
+        assert len(results) == count
+        for i in range(count):
+            _, _, n, exp = req(i)
+            assert results[ids[i]]["status"] == 0, i
+            assert np.array_equal(outs[i].numpy()[:n], exp), (i, bool(big[i]))
