@@ -243,7 +243,10 @@ __global__ __launch_bounds__(kThreads) void k_rng_scatter(const int* __restrict_
     extern __shared__ __align__(16) int lds[];
     int* out_s = lds;
     int* out_d = lds + kChunk;
-    __shared__ int hist[kScatterPer * kWaves * kMaxRanges];  // per (k, wave) slot and range: count, then first rank
+    // per (k, wave) slot and range: count, then first rank within the chunk
+    // (both below 2^16), R columns: with R <= 32 the workgroup needs under
+    // 80 KiB of LDS, so two share a CU
+    unsigned short* hist = reinterpret_cast<unsigned short*>(lds + 2 * kChunk);
     __shared__ int segsum[kWaves][kMaxRanges];
     __shared__ int total[kMaxRanges], lstart[kMaxRanges], gbase[kMaxRanges];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -252,7 +255,7 @@ __global__ __launch_bounds__(kThreads) void k_rng_scatter(const int* __restrict_
     const long long chunk = (long long)x * per + std::min(x, rem) + j;
     const long long e0 = chunk * kChunk;
     const int len = (int)std::min<long long>(kChunk, m - e0);
-    for (int i = t; i < kScatterPer * kWaves * kMaxRanges; i += kThreads) hist[i] = 0;
+    for (int i = t; i < kScatterPer * kWaves * R; i += kThreads) hist[i] = 0;
     int es[kScatterPer], ed[kScatterPer];
 #pragma unroll
     for (int k = 0; k < kScatterPer; ++k) {
@@ -274,7 +277,7 @@ __global__ __launch_bounds__(kThreads) void k_rng_scatter(const int* __restrict_
             peers &= bit ? bal : ~bal;
         }
         rank[k] = __popcll(peers & below);
-        if (valid && rank[k] == 0) hist[(k * kWaves + wave) * kMaxRanges + key[k]] = __popcll(peers);
+        if (valid && rank[k] == 0) hist[(k * kWaves + wave) * R + key[k]] = (unsigned short)__popcll(peers);
     }
     __syncthreads();
     // exclusive scan of each range's counts over the 128 slots in element
@@ -285,7 +288,7 @@ __global__ __launch_bounds__(kThreads) void k_rng_scatter(const int* __restrict_
     const int r = t & 63, seg = t >> 6;
     int sum = 0;
     if (r < R)
-        for (int s = 0; s < kSegSlots; ++s) sum += hist[(seg * kSegSlots + s) * kMaxRanges + r];
+        for (int s = 0; s < kSegSlots; ++s) sum += hist[(seg * kSegSlots + s) * R + r];
     segsum[seg][r] = sum;
     __syncthreads();
     if (t < kMaxRanges) {
@@ -301,9 +304,9 @@ __global__ __launch_bounds__(kThreads) void k_rng_scatter(const int* __restrict_
     if (r < R) {
         int run = segsum[seg][r];
         for (int s = 0; s < kSegSlots; ++s) {
-            const int i = (seg * kSegSlots + s) * kMaxRanges + r;
+            const int i = (seg * kSegSlots + s) * R + r;
             const int v = hist[i];
-            hist[i] = run;
+            hist[i] = (unsigned short)run;
             run += v;
         }
     }
@@ -323,7 +326,7 @@ __global__ __launch_bounds__(kThreads) void k_rng_scatter(const int* __restrict_
 #pragma unroll
     for (int k = 0; k < kScatterPer; ++k) {
         if (k * kThreads + t < len) {
-            const int pos = lstart[key[k]] + hist[(k * kWaves + wave) * kMaxRanges + key[k]] + rank[k];
+            const int pos = lstart[key[k]] + hist[(k * kWaves + wave) * R + key[k]] + rank[k];
             out_s[pos] = es[k];
             out_d[pos] = ed[k];
         }
@@ -336,6 +339,13 @@ __global__ __launch_bounds__(kThreads) void k_rng_scatter(const int* __restrict_
         osrc[slot] = out_s[i];
         odst[slot] = v;
     }
+}
+
+// dynamic LDS of the second-pass scatter: the chunk in range order and the
+// per-slot counts of R ranges
+static size_t rng_scatter_lds(int R)
+{
+    return kScatterLds + (size_t)kScatterPer * kWaves * R * sizeof(unsigned short);
 }
 
 void reorder_geometry(const DeviceInfo& d, long long m, int n, Reorder* r, int dshift)
@@ -357,7 +367,7 @@ void reorder_geometry(const DeviceInfo& d, long long m, int n, Reorder* r, int d
             r->dshift = dshift;
             r->R = R;
             (void)hipFuncSetAttribute((const void*)k_rng_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)kScatterLds);
+                                      (int)rng_scatter_lds(R));
         }
     }
     r->m = m;
@@ -412,7 +422,7 @@ int enqueue_reorder(const Reorder& r, const int* src, const int* dst, hipStream_
                        r.shift, r.K, (const int*)r.cnt, (const int*)r.part, s1, d1);
     if (r.R) {
         enqueue_counts(r, d1, r.dshift, r.R, r.cnt2, r.part2, stream);
-        hipLaunchKernelGGL(k_rng_scatter, dim3((unsigned)r.chunks), dim3(kThreads), kScatterLds, stream,
+        hipLaunchKernelGGL(k_rng_scatter, dim3((unsigned)r.chunks), dim3(kThreads), rng_scatter_lds(r.R), stream,
                            (const int*)s1, (const int*)d1, r.m, r.dshift, r.R, (const int*)r.cnt2,
                            (const int*)r.part2, r.src2, r.dst2);
     }
