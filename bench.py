@@ -184,6 +184,25 @@ def roofline(order, m, r, figures):
     return roof
 
 
+def full_order_roofline(contour, s, d, n, m, r):
+    """Roofline of a chase-to-root solve: its algorithmic bytes are the edge
+    stream (8 B per edge-sweep) plus 4 B per chain read, counted in one
+    instrumented solve (contour_cc_count_reads); the timed solves r give the
+    sweeps and the kernel time."""
+    _, st, reads = contour.cc_count_reads(s, d, n, order="full")
+    sw_c = contour.read_stats(st).sweeps_executed
+    reads_per_edge_sweep = int(reads.item()) / float(m * max(sw_c, 1))
+    sweeps = statistics.mean(x[1] for x in r["stats"])
+    kernel_ms = statistics.mean(r["kernel_ms"])
+    bpe = 8 + 4 * reads_per_edge_sweep
+    achieved = sweeps * m * bpe / (kernel_ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": "k_persistent",
+            "kernel_ms": round(kernel_ms, 4), "bytes_per_edge_sweep": round(bpe, 3),
+            "chain_reads_per_edge_sweep": round(reads_per_edge_sweep, 4),
+            "chain_reads_from": "one contour_cc_count_reads solve, %d sweeps" % sw_c}
+
+
 def summary(r, m):
     sw = [x[1] for x in r["stats"]]
     mean = statistics.mean(r["step_ms"])
@@ -208,6 +227,8 @@ def bench_plain_extra(contour, torch, name, seed, steps, modes, exact=None):
         res = summary(r, m)
         res["exact"] = bool(np.array_equal(r["labels"].cpu().numpy(), exact))
         order = opts.get("order", 2)
+        if opts == dict(order="full"):
+            res["roofline"] = full_order_roofline(contour, s, d, n, m, r)
         if opts.get("driver", "persistent") == "persistent" and opts.get("write", "plain") == "plain" and \
                 len(opts) <= 1:
             res["roofline"] = roofline(order, m, r, profile_figures(name) if not opts else None)
@@ -592,6 +613,8 @@ def main():
             modes[key]["exact"] = bool(np.array_equal(rr["labels"].cpu().numpy(), exact))
             if key == "order_3":
                 modes[key]["roofline"] = roofline(3, m, rr, None)
+            if key == "order_full":
+                modes[key]["roofline"] = full_order_roofline(contour, s, d, n, m, rr)
             del rr
         extras[args.workload + "_modes"] = modes
         del s, d

@@ -180,6 +180,21 @@ int contour_cc_ex(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
                   int32_t* labels_inout, const contour_opts_t* opts, contour_stats_t* stats,
                   contour_stream_t stream);
 
+/* contour_cc_count_reads: an instrumented contour_cc_ex (persistent driver)
+ * that also counts the label reads of the operator's chains, for measuring
+ * the traffic of operators whose reads per edge are not fixed.  For every
+ * edge and sweep run with an order above 3 or CONTOUR_ORDER_FULL, the reads
+ * of the chains w, L[w], ... and v, L[v], ... up to level h or to the root
+ * (Definition 3; the reads that decide z and the early convergence check) are
+ * added to *reads (device uint64, not cleared first).  Sweeps of orders 1..3
+ * read exactly 2h labels per edge and are not counted.  The extra work is one
+ * addition per read and one atomic per workgroup; labels and stats are those
+ * of contour_cc_ex.  Returns as contour_cc_ex; CONTOUR_EINVAL for a NULL reads,
+ * CONTOUR_ENOTSUP with the host-loop driver. */
+int contour_cc_count_reads(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
+                           int32_t* labels_inout, const contour_opts_t* opts, contour_stats_t* stats,
+                           uint64_t* reads, contour_stream_t stream);
+
 /* contour_reserve: allocate, up front, the workspace that contour_cc,
  * contour_cc_ex (persistent driver) and contour_group_edges need on `stream`
  * for graphs of up to m edges and n vertices under `opts` (NULL: defaults):

@@ -130,6 +130,26 @@ def cc_ex(src, dst, n: int, labels=None, stream=None, stats: bool = True, **opts
     return labels, st
 
 
+def cc_count_reads(src, dst, n: int, labels=None, stream=None, **opts):
+    """contour_cc_count_reads: (labels, stats_tensor, reads_tensor) where
+    reads_tensor is a device int64[1] holding the label reads of the chains
+    of every sweep run with an order above 3 or chase-to-root."""
+    torch = _torch()
+    _check_edges(src, dst)
+    if labels is None:
+        labels = torch.empty(max(int(n), 0), dtype=torch.int32, device=src.device)
+    o = make_opts(**opts)
+    st = torch.zeros(4, dtype=torch.int32, device=src.device)
+    reads = torch.zeros(1, dtype=torch.int64, device=src.device)
+    rc = load().contour_cc_count_reads(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                       src.numel(), int(n), ctypes.c_void_p(labels.data_ptr()),
+                                       ctypes.byref(o), ctypes.c_void_p(st.data_ptr()),
+                                       ctypes.c_void_p(reads.data_ptr()), _stream_ptr(stream))
+    if rc != OK:
+        raise ContourError(rc, "contour_cc_count_reads")
+    return labels, st, reads
+
+
 def reserve(m: int, n: int, stream=None, **opts):
     """contour_reserve: allocate the stream's workspace for graphs of up to m
     edges and n vertices, so that later solves on the stream within these

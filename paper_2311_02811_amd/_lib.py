@@ -71,6 +71,9 @@ SIGNATURES = {
     "contour_cc_add_edges": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                             ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ContourOpts),
                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "contour_cc_count_reads": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                              ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ContourOpts),
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "contour_reserve": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ContourOpts),
                                        ctypes.c_void_p]),
     "contour_cc_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,

@@ -81,6 +81,8 @@ struct SolveArgs {
     int win_margin;      // labels staged past the last source block of a task
     int xq_units;        // persistent driver: 0, one task counter for the whole GPU; else
                          // per-XCD queues of xq_units strided task groups per sweep
+    unsigned long long* reads = nullptr;  // instrumented solve: label reads of orders above 3
+                                          // (and chase-to-root) are added here; else null
 };
 
 // Edge ids are streamed once per sweep: non-temporal loads keep them from
@@ -284,9 +286,14 @@ __device__ __forceinline__ bool tile_order3(const LAB& lab, const int (&w)[EPT],
 // chain; any value it reads is a valid label, and if its reads differ from
 // the first walk's, some other edge stored in this sweep, so a sweep that
 // reports a change always makes one.
+//
+// nread (may be null) counts the label reads of the first walk: the reads
+// that MM^h prescribes (levels 1..h, or up to the root), for measuring the
+// chase-to-root operator's traffic.
 template <int EPT, bool ATOMIC, class LAB>
 __device__ __forceinline__ bool tile_orderh(const LAB& lab, const int (&w)[EPT],
-                                            const int (&v)[EPT], const bool (&ok)[EPT], int h)
+                                            const int (&v)[EPT], const bool (&ok)[EPT], int h,
+                                            int* nread = nullptr)
 {
     int cw[EPT], cv[EPT], fw[EPT], fv[EPT];
     bool dw[EPT], dv[EPT];
@@ -306,6 +313,7 @@ __device__ __forceinline__ bool tile_orderh(const LAB& lab, const int (&w)[EPT],
             int nw = cw[k], nv = cv[k];
             if (!dw[k]) nw = lab.ld(cw[k]);
             if (!dv[k]) nv = lab.ld(cv[k]);
+            if (nread) *nread += (dw[k] ? 0 : 1) + (dv[k] ? 0 : 1);
             if (lvl == 0) {
                 fw[k] = nw;
                 fv[k] = nv;
@@ -351,7 +359,8 @@ __device__ __forceinline__ bool tile_orderh(const LAB& lab, const int (&w)[EPT],
 template <int ORDER, int EPT, int BLOCK, bool ATOMIC, class LAB, int DEPTH = 4>
 __device__ __forceinline__ bool run_tiles(const int* __restrict__ src, const int* __restrict__ dst,
                                           const LAB& lab, long long first, long long count,
-                                          long long stride, long long m, unsigned n, int h, int& rerr)
+                                          long long stride, long long m, unsigned n, int h, int& rerr,
+                                          int* nread = nullptr)
 {
     const long long tile_edges = (long long)BLOCK * EPT;
     const long long step = stride * tile_edges;
@@ -379,7 +388,7 @@ __device__ __forceinline__ bool run_tiles(const int* __restrict__ src, const int
             if (ORDER == 1) pred |= tile_order1<EPT, ATOMIC>(lab, w[d], v[d], ok[d]);
             else if (ORDER == 2) pred |= tile_order2<EPT, ATOMIC>(lab, w[d], v[d], ok[d]);
             else if (ORDER == 3) pred |= tile_order3<EPT, ATOMIC>(lab, w[d], v[d], ok[d]);
-            else pred |= tile_orderh<EPT, ATOMIC>(lab, w[d], v[d], ok[d], h);
+            else pred |= tile_orderh<EPT, ATOMIC>(lab, w[d], v[d], ok[d], h, nread);
         }
         base += (long long)DEPTH * step;
     }
@@ -397,7 +406,8 @@ struct TileDepth {
 template <int EPT, int BLOCK, bool ATOMIC, class LAB, int DEPTH = TileDepth<EPT, BLOCK>::value>
 __device__ __forceinline__ bool run_tiles_lab(const int* __restrict__ src, const int* __restrict__ dst,
                                               const LAB& lab, long long first, long long count,
-                                              long long stride, long long m, unsigned n, int h, int& rerr)
+                                              long long stride, long long m, unsigned n, int h, int& rerr,
+                                              int* nread = nullptr)
 {
     switch (h) {
     case 1: return run_tiles<1, EPT, BLOCK, ATOMIC, LAB, DEPTH>(src, dst, lab, first, count, stride, m, n, h, rerr);
@@ -408,7 +418,8 @@ __device__ __forceinline__ bool run_tiles_lab(const int* __restrict__ src, const
         // vertices: chase-to-root is the order n operator, and the bound also
         // caps every walk.
         if (h < 0 || (unsigned)h > n) h = (int)n;
-        return run_tiles<0, EPT, BLOCK, ATOMIC, LAB, DEPTH>(src, dst, lab, first, count, stride, m, n, h, rerr);
+        return run_tiles<0, EPT, BLOCK, ATOMIC, LAB, DEPTH>(src, dst, lab, first, count, stride, m, n, h, rerr,
+                                                            nread);
     }
 }
 
@@ -544,10 +555,10 @@ template <int EPT, int BLOCK, bool ATOMIC>
 __device__ __forceinline__ bool run_tiles_order(const int* __restrict__ src, const int* __restrict__ dst,
                                                 const int* R, int* W, long long first, long long count,
                                                 long long stride, long long m, unsigned n, int h,
-                                                int& rerr)
+                                                int& rerr, int* nread = nullptr)
 {
     const FlatLabels lab{R, W};
-    return run_tiles_lab<EPT, BLOCK, ATOMIC>(src, dst, lab, first, count, stride, m, n, h, rerr);
+    return run_tiles_lab<EPT, BLOCK, ATOMIC>(src, dst, lab, first, count, stride, m, n, h, rerr, nread);
 }
 
 // Loop control read back from shared memory must be visibly uniform: the

@@ -329,7 +329,7 @@ __device__ __forceinline__ void write_back_window(const int* w, const unsigned* 
 // store.
 template <int EPT, int BLOCK, bool ATOMIC>
 __device__ __forceinline__ bool window_task(const SolveArgs& a, long long first_tile, long long count, int order,
-                                            int& rerr)
+                                            int& rerr, int* nread = nullptr)
 {
     extern __shared__ __align__(16) int dyn_lds[];
     __shared__ unsigned s_lo, s_cnt;
@@ -362,7 +362,7 @@ __device__ __forceinline__ bool window_task(const SolveArgs& a, long long first_
     __syncthreads();
     const WindowLabels lab{wl, dirty, lo, cnt, a.L, label_buffer(a.L, a.n), a.n * 4u, hkey, hval};
     const bool pred = run_tiles_lab<EPT, BLOCK, ATOMIC, WindowLabels, 1>(
-        a.src, a.dst, lab, first_tile, count, 1, a.m, a.n, order, rerr);
+        a.src, a.dst, lab, first_tile, count, 1, a.m, a.n, order, rerr, nread);
     __syncthreads();
     for (unsigned i = threadIdx.x; i < (unsigned)kHubSlots; i += BLOCK) {
         const int k = hkey[i];
@@ -420,6 +420,8 @@ __device__ __forceinline__ void persistent_solve(const SolveArgs& a)
     // per thread: some task since the last publication changed a label /
     // met an out-of-range id
     int changed = 0, rerr = 0;
+    int nread = 0;  // instrumented solve: label reads of this thread
+    int* const count_reads = a.reads ? &nread : nullptr;
     for (;;) {
         if (!uniform(s_go)) break;
         const long long t = uniform(s_task);
@@ -429,10 +431,10 @@ __device__ __forceinline__ void persistent_solve(const SolveArgs& a)
         const int order = order_of_sweep(a.sched, (int)sweep);
         bool pred;
         if (WIN)
-            pred = window_task<EPT, BLOCK, ATOMIC>(a, first, count, order, rerr);
+            pred = window_task<EPT, BLOCK, ATOMIC>(a, first, count, order, rerr, count_reads);
         else
             pred = run_tiles_order<EPT, BLOCK, true>(a.src, a.dst, a.L, a.L, first, count, 1, a.m, a.n, order,
-                                                     rerr);
+                                                     rerr, count_reads);
         changed |= pred ? 1 : 0;
         // take the next task; only a move to another sweep (or the end)
         // publishes, which needs every store of the workgroup drained and
@@ -457,6 +459,15 @@ __device__ __forceinline__ void persistent_solve(const SolveArgs& a)
             s_task = next;
         }
         __syncthreads();
+    }
+    if (a.reads) {
+        // instrumented solve: one global add per workgroup
+        __shared__ unsigned long long s_reads;
+        if (threadIdx.x == 0) s_reads = 0;
+        __syncthreads();
+        atomicAdd(&s_reads, (unsigned long long)nread);
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(a.reads, s_reads);
     }
 }
 

@@ -524,7 +524,7 @@ static int run_hostloop(const DeviceInfo& d, const Resolved& r0, const int* src,
 }
 
 static int run_solve(const int* src, const int* dst, long long m, int n, int* L, const Resolved& r,
-                     contour_stats_t* stats, hipStream_t stream)
+                     contour_stats_t* stats, hipStream_t stream, unsigned long long* reads = nullptr)
 {
     DeviceInfo d;
     int rc = device_info(&d);
@@ -544,6 +544,7 @@ static int run_solve(const int* src, const int* dst, long long m, int n, int* L,
     PersistentLaunch p;
     rc = prepare_persistent(d, r, src, dst, m, n, L, ws->ctl, scratch, &p);
     if (rc) return rc;
+    p.args.reads = reads;
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;
     timing_events(&ev_begin, &ev_end);
     return enqueue_persistent(p, stats, stream, ev_begin, ev_end);
@@ -598,6 +599,22 @@ int contour_reserve(int64_t m, int32_t n, const contour_opts_t* opts, contour_st
         need = std::max(need, contour::reorder_table_elems(ro));
     }
     return contour::workspace_scratch(ws, s, need);
+}
+
+int contour_cc_count_reads(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int32_t* labels_inout,
+                           const contour_opts_t* opts, contour_stats_t* stats, uint64_t* reads,
+                           contour_stream_t stream)
+{
+    if (m < 0 || n < 0 || !reads) return CONTOUR_EINVAL;
+    if (n > 0 && !labels_inout) return CONTOUR_EINVAL;
+    if (m > 0 && (!src || !dst)) return CONTOUR_EINVAL;
+    contour::Resolved r;
+    int rc = contour::resolve_opts(opts, &r);
+    if (rc) return rc;
+    if (r.driver != CONTOUR_DRIVER_PERSISTENT) return CONTOUR_ENOTSUP;
+    if (n == 0) return contour_cc_ex(src, dst, m, n, labels_inout, opts, stats, stream);
+    return contour::run_solve(src, dst, m, n, labels_inout, r, stats, (hipStream_t)stream,
+                              reinterpret_cast<unsigned long long*>(reads));
 }
 
 int contour_cc(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int32_t* labels_out,

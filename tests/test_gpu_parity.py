@@ -470,3 +470,32 @@ def test_config_rmat_full(contour):
         lab, st = contour.cc_ex(s, d, n, **mode)
         assert np.array_equal(lab.cpu().numpy(), exp), mode
         print("rmat %r: %d sweeps" % (mode, contour.read_stats(st).sweeps_executed))
+
+
+def test_count_reads_at_the_fixed_point(contour):
+    # contour_cc_count_reads counts the chain reads of orders above 3 and
+    # chase-to-root.  Warm-started from the exact labels, the solve is one
+    # sweep that changes nothing, so the count is fixed: a chain from x reads
+    # L[x] and, when x is not a root, L[L[x]] = L[x] as well -- one read from
+    # a root, two from any other vertex, for both endpoints of every edge.
+    for (src, dst), n in ((graphgen.grid_holes(300, 200, 0.1, 31), 60000),
+                          (graphgen.rmat(16, 8, 32), 1 << 16),
+                          (graphgen.rmat(21, 16, 33), 1 << 21)):
+        exp = oracle.uf_labels(src, dst, n)
+        root = exp == np.arange(n)
+        want = int(np.sum(np.where(root[src], 1, 2)) + np.sum(np.where(root[dst], 1, 2)))
+        s, d = dev(src), dev(dst)
+        for mode in (dict(order="full"), dict(order=5), dict(order="full", reorder="on"),
+                     dict(order="full", dst_ranges="on")):
+            lab = dev(exp)
+            lab, st, reads = contour.cc_count_reads(s, d, n, labels=lab, warm_start=True, **mode)
+            stats = contour.read_stats(st)
+            banner("count reads n=%d m=%d %r: %d" % (n, src.size, mode, int(reads.item())))
+            assert stats.status == 0 and stats.sweeps_executed == 1 and stats.sweeps_with_writes == 0
+            assert np.array_equal(lab.cpu().numpy(), exp)
+            assert int(reads.item()) == want, mode
+        # orders up to 3 are not counted; a cold solve counts at least one read per endpoint and sweep
+        _, _, reads = contour.cc_count_reads(s, d, n, order=2)
+        assert int(reads.item()) == 0
+        _, st, reads = contour.cc_count_reads(s, d, n, order="full")
+        assert int(reads.item()) >= 2 * src.size * contour.read_stats(st).sweeps_executed
