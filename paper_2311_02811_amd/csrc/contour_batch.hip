@@ -559,6 +559,7 @@ static int create_plan(const contour_batch_t* b, const contour_opts_t* opts, con
         rc2.ept = ept[2];
         rc2.grid = 0;
         rc2.reorder = CONTOUR_REORDER_OFF;
+        rc2.solo = false;
         p->multi_kernel = pick_multi(block[2], ept[2], r.atomic);
         int occ = 0;
         if (e == hipSuccess)

@@ -164,6 +164,7 @@ int resolve_opts(const contour_opts_t* o, Resolved* r)
     r->reorder = o->reorder;
     r->window = o->window;
     r->dst_ranges = o->dst_ranges;
+    r->solo = true;
     return CONTOUR_OK;
 }
 

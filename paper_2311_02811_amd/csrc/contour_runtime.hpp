@@ -68,6 +68,7 @@ struct Resolved {
     int reorder;
     int window;
     int dst_ranges;
+    bool solo;  // a single graph on the whole GPU (batched plans clear it for their class-2 graphs)
 };
 
 // Wall-clock ticks a single solve may run before the watchdog stops it

@@ -256,11 +256,17 @@ static void auto_geometry(const DeviceInfo& d, long long m, Resolved* r)
 
 // Persistent tasks: every task takes one counter increment, and every
 // workgroup publishes once per sweep, so tasks are large: m / 256 edges,
-// between 4096 and 65536 (measured best on the MI355X for graphs from 0.5 M
-// to 268 M edges).
-static int auto_tiles_per_task(long long m, long long tile_edges)
+// between 4096 and 65536.  A single graph below 4 M edges takes m / 64 edges
+// per task (at least 4096), so its solve runs on about 64 workgroups: each
+// works through more consecutive edges per sweep, which carries labels
+// further within a sweep (measured on the MI355X: ER with 524,288 edges 2
+// sweeps and 0.141 ms against 3 sweeps and 0.164 ms on 128 workgroups; with
+// 2 M edges 0.33 ms against 0.39).  Many graphs solved side by side (batched
+// plans) keep m / 256.
+static int auto_tiles_per_task(long long m, long long tile_edges, bool solo)
 {
-    const long long want = std::max<long long>(4096, std::min<long long>(65536, m / 256));
+    long long want = std::max<long long>(4096, std::min<long long>(65536, m / 256));
+    if (solo && m < (4LL << 20)) want = std::max<long long>(4096, m / 64);
     return (int)std::max<long long>(1, want / tile_edges);
 }
 
@@ -349,7 +355,7 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
         int occ = 0;
         CONTOUR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)p.kernel, r.block, p.lds));
         const long long resident = (long long)std::max(occ, 1) * d.cus;
-        int tpt = r.chunk_tiles ? r.chunk_tiles : auto_tiles_per_task(m, tile_edges);
+        int tpt = r.chunk_tiles ? r.chunk_tiles : auto_tiles_per_task(m, tile_edges, r.solo);
         if (win && !r.chunk_tiles) {
             // A window is staged per task.  Tasks of 32 Ki edges, about one
             // source block of a sparse graph; where blocks hold many more
