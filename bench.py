@@ -161,8 +161,10 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
 
 
-def roofline(order, m, r, figures):
-    """Roofline object of the sweep kernel from a time_gpu result."""
+def roofline(order, m, r, figures, n=None):
+    """Roofline object of the sweep kernel from a time_gpu result.  With n,
+    also the compulsory-traffic rate: each sweep reads the edges once and the
+    labels once and writes them once (8m + 8n bytes)."""
     bpe = bytes_per_edge_sweep(order)
     if bpe is None:
         return None
@@ -173,6 +175,10 @@ def roofline(order, m, r, figures):
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
             "kernel": "k_persistent", "kernel_ms": round(kernel_ms, 4),
             "bytes_per_edge_sweep": bpe, "edge_sweeps_per_launch": sweeps * m}
+    if n is not None:
+        comp = sweeps * (8.0 * m + 8.0 * n) / (kernel_ms / 1e3) / 1e9
+        roof["compulsory_GBps"] = round(comp, 1)
+        roof["compulsory_frac"] = round(comp / HBM_PEAK_GBPS, 4)
     if figures:
         if "traffic" in figures:
             roof["traffic"] = figures["traffic"]
@@ -182,6 +188,40 @@ def roofline(order, m, r, figures):
         if "l2_hit_rate" in figures:
             roof["l2_hit_rate"] = figures["l2_hit_rate"]
     return roof
+
+
+def gather_ceilings(contour, torch, s, d, n, sweep_ms):
+    """The sweep's memory access pattern without its arithmetic
+    (contour_gather_ceiling) on the copy the default solve sweeps: edges
+    only, edges + destination gathers, edges + both gathers; each the best of
+    5.  sweep_ms is the measured sweep kernel time per sweep."""
+    lib = contour.load()
+    m = s.numel()
+    ranges = n > (1 << 20) and m >= 4 * n
+    gs, gd = contour.group_edges(s, d, n, ranges=ranges)
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    labels = torch.arange(n, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    out = {"layout": "grouped by source block%s" % (", then destination range" if ranges else "")}
+    for mode, key in ((0, "edges_ms"), (1, "edges_dst_gather_ms"), (2, "edges_both_gathers_ms")):
+        ts = []
+        for _ in range(5):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            rc = lib.contour_gather_ceiling(ctypes.c_void_p(gs.data_ptr()), ctypes.c_void_p(gd.data_ptr()), m,
+                                            ctypes.c_void_p(labels.data_ptr()), n, mode,
+                                            ctypes.c_void_p(sink.data_ptr()), ctypes.c_void_p(stream.cuda_stream))
+            b.record(stream)
+            if rc != 0:
+                raise RuntimeError("contour_gather_ceiling failed: %d" % rc)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        out[key] = round(min(ts), 4)
+    out["edges_GBps"] = round(8.0 * m / (out["edges_ms"] / 1e3) / 1e9, 1)
+    out["sweep_ms"] = round(sweep_ms, 4)
+    out["sweep_over_dst_gather_ceiling"] = round(sweep_ms / out["edges_dst_gather_ms"], 3)
+    del gs, gd
+    return out
 
 
 def full_order_roofline(contour, s, d, n, m, r):
@@ -226,12 +266,12 @@ def bench_plain_extra(contour, torch, name, seed, steps, modes, exact=None):
         r = time_gpu(contour, torch, s, d, n, steps, 1, opts)
         res = summary(r, m)
         res["exact"] = bool(np.array_equal(r["labels"].cpu().numpy(), exact))
-        order = opts.get("order", 2)
-        if opts == dict(order="full"):
+        if not opts:
+            res["roofline"] = roofline(2, m, r, profile_figures(name), n)
+        elif opts == dict(order=3):
+            res["roofline"] = roofline(3, m, r, None, n)
+        elif opts == dict(order="full"):
             res["roofline"] = full_order_roofline(contour, s, d, n, m, r)
-        if opts.get("driver", "persistent") == "persistent" and opts.get("write", "plain") == "plain" and \
-                len(opts) <= 1:
-            res["roofline"] = roofline(order, m, r, profile_figures(name) if not opts else None)
         out[key] = res
     return out, (src, dst, n, exact)
 
@@ -551,7 +591,7 @@ def main():
     value = m / (ms_per_step / 1e3)
     default_cfg = (args.reorder, args.block, args.edges_per_thread, args.chunk_tiles, args.write,
                    args.driver, args.order, args.dst_ranges) == ("auto", 0, 0, 0, "plain", "persistent", "2", "auto")
-    roof = roofline(order, m, r, profile_figures(args.workload) if default_cfg else None)
+    roof = roofline(order, m, r, profile_figures(args.workload) if default_cfg else None, n)
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -577,6 +617,7 @@ def main():
         "roofline": roof,
     }
     gpu_labels = r["labels"].cpu().numpy()
+    r_kernel_ms = r["kernel_ms"]
     del r
     exact = None
     if not args.no_cpu_baseline:
@@ -596,6 +637,9 @@ def main():
         if not args.no_cpu_baseline:
             log("CPU: the paper's multicore design (%.0f s budget)" % args.cpu_seconds)
             extras["cpu_contour_omp"] = cpu_contour_omp(src, dst, n, exact, args.cpu_seconds)
+        log("gather ceilings")
+        sweep_ms = roof["kernel_ms"] / out["sweeps"]["mean"] if roof else statistics.mean(r_kernel_ms) / out["sweeps"]["mean"]
+        extras["ceilings"] = gather_ceilings(contour, torch, s, d, n, sweep_ms)
         log("cold caches: 1 GiB written before each solve")
         rc = time_gpu(contour, torch, s, d, n, 5, 1, opts, cold_bytes=1 << 30)
         extras["cold"] = summary(rc, m)

@@ -371,6 +371,19 @@ int contour_cc_batched(const contour_batch_t* batch, const contour_opts_t* opts,
                        contour_stream_t stream);
 
 /* ------------------------------------------------------- profiling ---- */
+/* contour_gather_ceiling: a measurement kernel, the memory access pattern of
+ * a sweep without its arithmetic, for comparing a sweep's time with what the
+ * GPU can do with the same accesses.  It reads src[0..m) and dst[0..m) once
+ * and, with mode 1, gathers labels[dst[e]] for every edge (mode 2: also
+ * labels[src[e]]), ids outside [0, n) skipped; the edge list is cut into
+ * eight segments dealt to the eight XCDs, as the sweep's XCD queues deal a
+ * copy grouped by destination range.  Nothing is written but, practically
+ * never, sink[0] (device int32).  Enqueued on `stream`; time it with events.
+ * Returns CONTOUR_OK, CONTOUR_EINVAL or CONTOUR_EHIP. */
+int contour_gather_ceiling(const int32_t* src, const int32_t* dst, int64_t m, const int32_t* labels, int32_t n,
+                           int32_t mode, int32_t* sink, contour_stream_t stream);
+
+
 /* Optional timing hook for benchmarks.  When set (non-NULL hipEvent_t
  * handles), contour_cc / contour_cc_ex record `begin` on the call's stream
  * just before the first sweep kernel and `end` just after the last, so the

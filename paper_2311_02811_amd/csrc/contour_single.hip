@@ -153,6 +153,39 @@ __global__ void k_flatten(int* L, unsigned n, const Ctl* c)
     }
 }
 
+// ------------------------------------------------ measurement ----------
+// Ceiling of a sweep's memory access pattern without its arithmetic: stream
+// the edge arrays and (mode 1) gather L[dst], (mode 2) gather L[src] and
+// L[dst], summing what was read.  Workgroup b works on segment b & 7 of the
+// edge list (workgroups are dealt to the eight XCDs in turn), so on a copy
+// grouped by destination range each XCD gathers from its own ranges, as the
+// sweep's XCD queues arrange it.  Four edges per thread per step.
+__global__ __launch_bounds__(1024) void k_gather_ceiling(const int* __restrict__ src, const int* __restrict__ dst,
+                                                         long long m, const int* __restrict__ L, unsigned n,
+                                                         int mode, int* __restrict__ sink)
+{
+    const int x = blockIdx.x & 7;
+    const long long per = gridDim.x / 8, j = blockIdx.x / 8;
+    const long long lo = x * m / 8, hi = (x + 1) * m / 8;
+    int acc = 0;
+    for (long long e = lo + (j * 1024 + threadIdx.x) * 4; e < hi; e += per * 4096) {
+        int w[4], v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const long long i = std::min(e + k, hi - 1);
+            w[k] = ld_edge(src + i);
+            v[k] = ld_edge(dst + i);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            acc ^= w[k] ^ v[k];
+            if (mode >= 1 && (unsigned)v[k] < n) acc += L[v[k]];
+            if (mode >= 2 && (unsigned)w[k] < n) acc += L[w[k]];
+        }
+    }
+    if (acc == 0x7fffffff) sink[0] = acc;  // keeps the reads; practically never taken
+}
+
 // ----------------------------------------------------- dispatch ---------
 
 typedef void (*persistent_fn)(SolveArgs);
@@ -621,6 +654,23 @@ int contour_cc_count_reads(const int32_t* src, const int32_t* dst, int64_t m, in
     if (n == 0) return contour_cc_ex(src, dst, m, n, labels_inout, opts, stats, stream);
     return contour::run_solve(src, dst, m, n, labels_inout, r, stats, (hipStream_t)stream,
                               reinterpret_cast<unsigned long long*>(reads));
+}
+
+int contour_gather_ceiling(const int32_t* src, const int32_t* dst, int64_t m, const int32_t* labels, int32_t n,
+                           int32_t mode, int32_t* sink, contour_stream_t stream)
+{
+    if (m < 0 || n < 0 || mode < 0 || mode > 2 || !sink) return CONTOUR_EINVAL;
+    if (m > 0 && (!src || !dst)) return CONTOUR_EINVAL;
+    if (mode > 0 && n > 0 && !labels) return CONTOUR_EINVAL;
+    if (m == 0) return CONTOUR_OK;
+    contour::DeviceInfo d;
+    int rc = contour::device_info(&d);
+    if (rc) return rc;
+    const unsigned grid = (unsigned)std::max(8, (d.cus / 8) * 8 * 2);
+    hipLaunchKernelGGL(contour::k_gather_ceiling, dim3(grid), dim3(1024), 0, (hipStream_t)stream, src, dst,
+                       (long long)m, labels, (unsigned)n, mode, sink);
+    CONTOUR_HIP(hipGetLastError());
+    return CONTOUR_OK;
 }
 
 int contour_cc(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int32_t* labels_out,

@@ -111,3 +111,15 @@ def test_reserve_and_noalloc_argument_errors_without_touching_the_device():
     assert lib.contour_cc_noalloc(None, None, 0, 4, None, None, None, None) == contour.EINVAL
     assert lib.contour_cc_noalloc(None, None, 0, 0, None, ctypes.byref(o), None, None) == contour.EINVAL
     assert lib.contour_status_string(contour.ETOOBIG).startswith(b"input needs more")
+
+
+def test_gather_ceiling_and_count_reads_argument_errors_without_touching_the_device():
+    import paper_2311_02811_amd as contour
+    lib = contour.load()
+    p = ctypes.c_void_p(16)
+    assert lib.contour_gather_ceiling(p, p, 5, p, 4, 0, None, None) == contour.EINVAL   # no sink
+    assert lib.contour_gather_ceiling(p, p, 5, p, 4, 3, p, None) == contour.EINVAL      # bad mode
+    assert lib.contour_gather_ceiling(None, None, 5, p, 4, 1, p, None) == contour.EINVAL
+    assert lib.contour_gather_ceiling(None, None, 0, None, 0, 0, p, None) == contour.OK
+    assert lib.contour_cc_count_reads(None, None, 0, 0, None, None, None, None, None) == contour.EINVAL
+    assert lib.contour_cc_count_reads(None, None, -1, 4, None, None, None, p, None) == contour.EINVAL
