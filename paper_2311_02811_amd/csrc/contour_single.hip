@@ -159,29 +159,52 @@ __global__ void k_flatten(int* L, unsigned n, const Ctl* c)
 // L[dst], summing what was read.  Workgroup b works on segment b & 7 of the
 // edge list (workgroups are dealt to the eight XCDs in turn), so on a copy
 // grouped by destination range each XCD gathers from its own ranges, as the
-// sweep's XCD queues arrange it.  Four edges per thread per step.
+// sweep's XCD queues arrange it.  Four edges per thread per step, read with
+// one 16-byte load per array when both arrays are 16-byte aligned (segments
+// start on multiples of four edges), else one load per edge.
+__device__ __forceinline__ int ceiling_gathers(const int* __restrict__ L, unsigned n, int mode, const int (&w)[4],
+                                               const int (&v)[4], const bool (&ok)[4])
+{
+    int acc = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        acc ^= w[k] ^ v[k];
+        if (ok[k] && mode >= 1 && (unsigned)v[k] < n) acc += L[v[k]];
+        if (ok[k] && mode >= 2 && (unsigned)w[k] < n) acc += L[w[k]];
+    }
+    return acc;
+}
+
 __global__ __launch_bounds__(1024) void k_gather_ceiling(const int* __restrict__ src, const int* __restrict__ dst,
                                                          long long m, const int* __restrict__ L, unsigned n,
                                                          int mode, int* __restrict__ sink)
 {
     const int x = blockIdx.x & 7;
     const long long per = gridDim.x / 8, j = blockIdx.x / 8;
-    const long long lo = x * m / 8, hi = (x + 1) * m / 8;
+    const long long lo = ((long long)x * m / 8) & ~3LL;
+    const long long hi = x == 7 ? m : (((long long)x + 1) * m / 8) & ~3LL;
+    const bool vec = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0;
     int acc = 0;
     for (long long e = lo + (j * 1024 + threadIdx.x) * 4; e < hi; e += per * 4096) {
         int w[4], v[4];
+        bool ok[4];
+        if (vec && e + 4 <= hi) {
+            const edge4_t a = __builtin_nontemporal_load(reinterpret_cast<const edge4_t*>(src + e));
+            const edge4_t b = __builtin_nontemporal_load(reinterpret_cast<const edge4_t*>(dst + e));
+            w[0] = a.x, w[1] = a.y, w[2] = a.z, w[3] = a.w;
+            v[0] = b.x, v[1] = b.y, v[2] = b.z, v[3] = b.w;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const long long i = std::min(e + k, hi - 1);
-            w[k] = ld_edge(src + i);
-            v[k] = ld_edge(dst + i);
-        }
+            for (int k = 0; k < 4; ++k) ok[k] = true;
+        } else {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            acc ^= w[k] ^ v[k];
-            if (mode >= 1 && (unsigned)v[k] < n) acc += L[v[k]];
-            if (mode >= 2 && (unsigned)w[k] < n) acc += L[w[k]];
+            for (int k = 0; k < 4; ++k) {
+                ok[k] = e + k < hi;
+                const long long i = ok[k] ? e + k : hi - 1;
+                w[k] = ld_edge(src + i);
+                v[k] = ld_edge(dst + i);
+            }
         }
+        acc += ceiling_gathers(L, n, mode, w, v, ok);
     }
     if (acc == 0x7fffffff) sink[0] = acc;  // keeps the reads; practically never taken
 }
@@ -666,7 +689,8 @@ int contour_gather_ceiling(const int32_t* src, const int32_t* dst, int64_t m, co
     contour::DeviceInfo d;
     int rc = contour::device_info(&d);
     if (rc) return rc;
-    const unsigned grid = (unsigned)std::max(8, (d.cus / 8) * 8 * 2);
+    // two resident 1024-thread workgroups per CU, four launched per CU
+    const unsigned grid = (unsigned)std::max(8, (d.cus / 8) * 8 * 4);
     hipLaunchKernelGGL(contour::k_gather_ceiling, dim3(grid), dim3(1024), 0, (hipStream_t)stream, src, dst,
                        (long long)m, labels, (unsigned)n, mode, sink);
     CONTOUR_HIP(hipGetLastError());
