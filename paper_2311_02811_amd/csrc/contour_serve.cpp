@@ -8,7 +8,9 @@
 //      micro-batch of small requests (one workgroup per graph, one launch)
 //      or one large request (persistent multi-workgroup solve), admitting
 //      each request only when its device footprint fits the HBM budget;
-//   3. sleeps briefly when nothing changed.
+//   3. when nothing changed: yields while lanes are in flight (their
+//      completion is found by polling events), and waits for the next
+//      submission when nothing is in flight.
 // A lane is a stream plus the small tables its launches need, allocated once
 // at creation, so serving allocates device memory only through the request
 // pool (power-of-two size classes, reused, counted against the budget).
@@ -93,6 +95,7 @@ struct contour_server {
     std::thread engine;
     std::mutex mu;
     std::condition_variable cv_done;
+    std::condition_variable cv_work;  // the engine waits here when it has nothing in flight
     std::deque<contour::Request*> pending;  // submitted, not yet admitted
     std::deque<contour::Request*> finished;
     int64_t next_id = 1;
@@ -376,17 +379,25 @@ void engine_loop(contour_server* s)
             progress = true;
         }
         // 3. stop or wait
-        bool idle;
+        bool any_busy = false;
+        for (const Lane& L : s->lanes) any_busy |= L.busy;
         {
-            std::lock_guard<std::mutex> lock(s->mu);
-            idle = s->pending.empty();
-            if (s->stop && idle) {
-                bool any_busy = false;
-                for (const Lane& L : s->lanes) any_busy |= L.busy;
-                if (!any_busy) break;
+            std::unique_lock<std::mutex> lock(s->mu);
+            const bool idle = s->pending.empty();
+            if (s->stop && idle && !any_busy) break;
+            if (!progress && !any_busy) {
+                // nothing in flight: sleep until a submission or stop (at
+                // most 1 ms, so a request waiting for memory is retried)
+                const auto seen = s->submitted;
+                s->cv_work.wait_for(lock, std::chrono::milliseconds(1),
+                                    [&] { return s->stop || s->submitted != seen; });
+                continue;
             }
         }
-        if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(idle ? 50 : 10));
+        // lanes in flight: poll their events again soon, without sleeping
+        // (a sleep of the engine thread adds tens of microseconds to every
+        // request's latency)
+        if (!progress) std::this_thread::yield();
     }
 }
 
@@ -509,6 +520,7 @@ int contour_server_submit(contour_server_t s, const int32_t* h_src, const int32_
     ++s->submitted;
     s->pending.push_back(r);
     if (id_out) *id_out = r->id;
+    s->cv_work.notify_one();
     return CONTOUR_OK;
 }
 
@@ -551,6 +563,7 @@ int contour_server_destroy(contour_server_t s)
     {
         std::lock_guard<std::mutex> lock(s->mu);
         s->stop = true;
+        s->cv_work.notify_all();
     }
     if (s->engine.joinable()) s->engine.join();
     for (contour::Request* r : s->finished) delete r;
