@@ -499,3 +499,28 @@ def test_count_reads_at_the_fixed_point(contour):
         assert int(reads.item()) == 0
         _, st, reads = contour.cc_count_reads(s, d, n, order="full")
         assert int(reads.item()) >= 2 * src.size * contour.read_stats(st).sweeps_executed
+
+
+def test_gather_ceiling_measurement_kernel(contour):
+    # contour_gather_ceiling only reads: every mode returns OK and leaves the
+    # labels and edges as they were (aligned and unaligned edge arrays, a
+    # ragged tail, ids outside [0, n))
+    import ctypes
+    lib = contour.load()
+    src, dst = graphgen.rmat(16, 8, 41)
+    src[::101] = -1
+    n = 1 << 16
+    s, d = dev(src), dev(dst)
+    labels = torch.arange(n, dtype=torch.int32, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for off in (0, 1):
+        m = src.size - 3 - off
+        for mode in (0, 1, 2):
+            rc = lib.contour_gather_ceiling(ctypes.c_void_p(s.data_ptr() + 4 * off), ctypes.c_void_p(d.data_ptr() + 4 * off),
+                                            m, ctypes.c_void_p(labels.data_ptr()), n, mode,
+                                            ctypes.c_void_p(sink.data_ptr()), stream)
+            assert rc == contour.OK
+    torch.cuda.synchronize()
+    assert torch.equal(labels.cpu(), torch.arange(n, dtype=torch.int32))
+    assert np.array_equal(s.cpu().numpy(), src) and np.array_equal(d.cpu().numpy(), dst)
