@@ -434,9 +434,14 @@ struct FlatLabels {
 };
 
 // A window of the label array, ids [lo, lo + cnt), staged in LDS; ids
-// outside it are read and written in global memory G.  Stores into the
-// window mark a dirty bit, and the workgroup writes the dirty labels back
-// once at the end of its task.
+// outside it are read and written in global memory G.  The workgroup writes
+// the labels it lowered in the window back once at the end of its task.
+// Which ones those are is kept in the labels themselves: every staged label
+// carries the tag bit kLabelClean (labels are below 2^30 wherever windows are
+// used), a store into the window writes the untagged value, and a read masks
+// the tag off.  A store thus needs no second LDS operation to mark it, and a
+// smaller value always replaces a staged one under an atomic minimum too
+// (the tagged value is larger than any label).
 //
 // A gather issues an LDS read (clamped index) and, unless every lane of the
 // wave reads inside the window, a buffer load of G whose offset is pushed out
@@ -450,6 +455,7 @@ struct FlatLabels {
 // and wait for it.  Buffer offsets are 32-bit bytes, so label windows are
 // only used for n < 2^30 (a host-side rule).
 constexpr unsigned kBufferDataFormat32 = 4u << 15;  // buffer resource word 3: 32-bit elements
+constexpr int kLabelClean = 1 << 30;                // tag of a staged, unchanged window label
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t label_buffer(const int* G, unsigned n)
 {
@@ -472,7 +478,6 @@ __device__ __forceinline__ unsigned hub_slot(int x)
 
 struct WindowLabels {
     int* lds;
-    unsigned* dirty;
     unsigned lo;
     unsigned cnt;
     int* G;
@@ -489,7 +494,7 @@ struct WindowLabels {
         int vg = 0;
         if (__builtin_amdgcn_ballot_w64(!in) != 0)  // wave-uniform: skipped when every id is in the window
             vg = __builtin_amdgcn_raw_buffer_load_b32(rsrc, in ? oob : (unsigned)x * 4u, 0, 0);
-        return in ? vl : vg;
+        return in ? (vl & (kLabelClean - 1)) : vg;
     }
     template <bool ATOMIC>
     __device__ __forceinline__ void st(int x, int z) const
@@ -500,7 +505,6 @@ struct WindowLabels {
                 atomicMin(&lds[i], z);
             else
                 lds[i] = z;
-            atomicOr(&dirty[i >> 5], 1u << (i & 31));
         } else {
             const unsigned h = hub_slot(x);
             const int k = atomicCAS(&hkey[h], -1, x);

@@ -236,7 +236,8 @@ __device__ __forceinline__ void task_tiles(const SolveArgs& a, long long chunk, 
     *count = (chunk + 1) * a.ntiles / a.tasks - f;
 }
 
-// Stage cnt labels from global memory g into LDS w.  Every thread keeps
+// Stage cnt labels from global memory g into LDS w, each tagged with
+// kLabelClean (see WindowLabels).  Every thread keeps
 // kStageUnroll loads in flight before it writes any of them to LDS, 16 bytes
 // each when g is 16-byte aligned, so one workgroup has up to 64 KiB of label
 // reads outstanding instead of one 4-byte read per thread at a time.  Loads
@@ -258,7 +259,14 @@ __device__ __forceinline__ void stage_window(int* w, const int* g, unsigned cnt)
 #pragma unroll
             for (int u = 0; u < kStageUnroll; ++u) v[u] = g4[min(i0 + u * BLOCK, q - 1)];
 #pragma unroll
-            for (int u = 0; u < kStageUnroll; ++u) w4[min(i0 + u * BLOCK, q - 1)] = v[u];
+            for (int u = 0; u < kStageUnroll; ++u) {
+                int4 t = v[u];
+                t.x |= kLabelClean;
+                t.y |= kLabelClean;
+                t.z |= kLabelClean;
+                t.w |= kLabelClean;
+                w4[min(i0 + u * BLOCK, q - 1)] = t;
+            }
         }
         done = q << 2;
     }
@@ -267,11 +275,11 @@ __device__ __forceinline__ void stage_window(int* w, const int* g, unsigned cnt)
 #pragma unroll
         for (int u = 0; u < kStageUnroll; ++u) v[u] = g[min(i0 + u * BLOCK, cnt - 1)];
 #pragma unroll
-        for (int u = 0; u < kStageUnroll; ++u) w[min(i0 + u * BLOCK, cnt - 1)] = v[u];
+        for (int u = 0; u < kStageUnroll; ++u) w[min(i0 + u * BLOCK, cnt - 1)] = v[u] | kLabelClean;
     }
 }
 
-// Write the labels of window w whose dirty bit is set back to global memory
+// Write the labels of window w that a store lowered (untagged) back to global memory
 // (g = labels + lo, buffer resource rsrc over the labels, byte offset of g
 // in it goff).  Plain mode writes through to memory (sc1 stores: 16 bytes for
 // four dirty labels in a row, else 4 bytes each), atomic mode takes the
@@ -282,8 +290,8 @@ __device__ __forceinline__ void stage_window(int* w, const int* g, unsigned cnt)
 constexpr int kStoreWriteThrough = 16;  // buffer cache policy: sc1
 
 template <int BLOCK, bool ATOMIC>
-__device__ __forceinline__ void write_back_window(const int* w, const unsigned* dirty, int* g,
-                                                  __amdgpu_buffer_rsrc_t rsrc, unsigned goff, unsigned cnt)
+__device__ __forceinline__ void write_back_window(const int* w, int* g, __amdgpu_buffer_rsrc_t rsrc,
+                                                  unsigned goff, unsigned cnt)
 {
     typedef int v4i __attribute__((ext_vector_type(4)));
     const unsigned q = (cnt + 3) >> 2;
@@ -294,9 +302,14 @@ __device__ __forceinline__ void write_back_window(const int* w, const unsigned* 
 #pragma unroll
         for (int u = 0; u < kStageUnroll; ++u) {
             const unsigned idx = min(i0 + u * BLOCK, q - 1);
-            const unsigned j = idx * 4;
-            bits[u] = i0 + u * BLOCK < q ? (dirty[j >> 5] >> (j & 31)) & 15u : 0u;
             val[u] = w4[idx];
+            // lowered labels lack the tag; the lanes of a last, partial
+            // quad past cnt hold whatever the LDS held and are masked off
+            const unsigned j = idx * 4;
+            unsigned b = (val[u].x & kLabelClean ? 0u : 1u) | (val[u].y & kLabelClean ? 0u : 2u) |
+                         (val[u].z & kLabelClean ? 0u : 4u) | (val[u].w & kLabelClean ? 0u : 8u);
+            if (j + 4 > cnt) b &= (1u << (cnt - j)) - 1u;
+            bits[u] = i0 + u * BLOCK < q ? b : 0u;
         }
 #pragma unroll
         for (int u = 0; u < kStageUnroll; ++u) {
@@ -350,17 +363,15 @@ __device__ __forceinline__ bool window_task(const SolveArgs& a, long long first_
     const unsigned lo = uniform((int)s_lo);
     const unsigned cnt = uniform((int)s_cnt);
     int* wl = dyn_lds;
-    unsigned* dirty = reinterpret_cast<unsigned*>(dyn_lds + a.win_cap);
-    int* hkey = dyn_lds + a.win_cap + a.win_cap / 32;
+    int* hkey = dyn_lds + a.win_cap;
     int* hval = hkey + kHubSlots;
     stage_window<BLOCK>(wl, a.L + lo, cnt);
-    for (unsigned i = threadIdx.x; i < (cnt + 31) / 32; i += BLOCK) dirty[i] = 0;
     for (unsigned i = threadIdx.x; i < (unsigned)kHubSlots; i += BLOCK) {
         hkey[i] = -1;
         hval[i] = 0x7fffffff;
     }
     __syncthreads();
-    const WindowLabels lab{wl, dirty, lo, cnt, a.L, label_buffer(a.L, a.n), a.n * 4u, hkey, hval};
+    const WindowLabels lab{wl, lo, cnt, a.L, label_buffer(a.L, a.n), a.n * 4u, hkey, hval};
     const bool pred = run_tiles_lab<EPT, BLOCK, ATOMIC, WindowLabels, 1>(
         a.src, a.dst, lab, first_tile, count, 1, a.m, a.n, order, rerr, nread);
     __syncthreads();
@@ -368,7 +379,7 @@ __device__ __forceinline__ bool window_task(const SolveArgs& a, long long first_
         const int k = hkey[i];
         if (k >= 0) __hip_atomic_fetch_min(a.L + k, hval[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    write_back_window<BLOCK, ATOMIC>(wl, dirty, a.L + lo, lab.rsrc, lo * 4u, cnt);
+    write_back_window<BLOCK, ATOMIC>(wl, a.L + lo, lab.rsrc, lo * 4u, cnt);
     return pred;
 }
 

@@ -383,11 +383,11 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
         persistent_fn kxq = win && p.ro.R > 0 ? pick_xq(r.block, r.ept, r.atomic) : nullptr;
         if (kxq) std::swap(p.kernel, kxq);
         if (win) {
-            // the largest window (labels + one dirty bit each) that fits the
-            // LDS of one workgroup, a multiple of 32 labels
-            // (after the hub table of out-of-window stores)
+            // the largest window that fits the LDS of one workgroup, a
+            // multiple of 32 labels (after the hub table of out-of-window
+            // stores)
             const long long bytes = std::max(0, d.max_lds_per_block - 2048 - 8 * kHubSlots);
-            long long cap = ((bytes * 32) / 132) & ~31LL;
+            long long cap = (bytes / 4) & ~31LL;
             if (r.window > 0) cap = std::min<long long>(cap, (long long)r.window & ~31LL);
             a.win_cap = (int)std::min<long long>(cap, ((long long)n + 31) & ~31LL);
             a.win_shift = p.ro.shift;
@@ -399,7 +399,7 @@ int prepare_persistent(const DeviceInfo& d, const Resolved& r0, const int* src, 
                 a.win_shift = 0;
                 a.win_margin = 0;
             }
-            p.lds = (size_t)a.win_cap * 4 + (size_t)((a.win_cap + 31) / 32) * 4 + (size_t)kHubSlots * 8;
+            p.lds = (size_t)a.win_cap * 4 + (size_t)kHubSlots * 8;
             CONTOUR_HIP(hipFuncSetAttribute((const void*)p.kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                             (int)p.lds));
             if (kxq)
