@@ -647,7 +647,11 @@ def main():
         del rc
         log("modes on %s" % args.workload)
         modes = {}
+        # operator choice (Section III-B-4): C-1, and the mixed schedules
+        # C-11mm (order 1 for the first sweep) and C-1m1m, at order 2
         for key, o2 in (("order_3", dict(order=3)), ("order_full", dict(order="full")),
+                        ("order_1", dict(order=1)), ("schedule_11mm", dict(schedule="11mm", k1=1)),
+                        ("schedule_1m1m", dict(schedule="1m1m")),
                         ("dst_ranges_off", dict(dst_ranges="off")),
                         ("write_atomic", dict(write="atomic")),
                         ("hostloop_plain", dict(driver="hostloop")),
@@ -655,8 +659,8 @@ def main():
             rr = time_gpu(contour, torch, s, d, n, 3, 1, o2)
             modes[key] = summary(rr, m)
             modes[key]["exact"] = bool(np.array_equal(rr["labels"].cpu().numpy(), exact))
-            if key == "order_3":
-                modes[key]["roofline"] = roofline(3, m, rr, None)
+            if key in ("order_3", "order_1"):
+                modes[key]["roofline"] = roofline(int(key[-1]), m, rr, None)
             if key == "order_full":
                 modes[key]["roofline"] = full_order_roofline(contour, s, d, n, m, rr)
             del rr
@@ -670,6 +674,7 @@ def main():
             extras[name], _ = bench_plain_extra(
                 contour, torch, name, args.seed, 5,
                 [("order_2", dict()), ("order_3", dict(order=3)), ("order_full", dict(order="full")),
+                 ("schedule_11mm", dict(schedule="11mm", k1=1)), ("schedule_1m1m", dict(schedule="1m1m")),
                  ("hostloop_plain", dict(driver="hostloop")),
                  ("hostloop_atomic", dict(driver="hostloop", write="atomic"))])
             torch.cuda.empty_cache()
