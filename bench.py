@@ -190,6 +190,35 @@ def roofline(order, m, r, figures, n=None):
     return roof
 
 
+def bench_merge(contour, torch, n=1 << 24, reps=20):
+    """contour_merge_min, the combine step of the edge-split design, on two
+    label states of n labels where the peer is smaller everywhere (every
+    label is read twice and written once: 12 bytes per label)."""
+    idx = torch.arange(n, dtype=torch.int32, device="cuda")
+    peer = (idx // 2).contiguous()
+    base = idx.clone()
+    lab = torch.empty_like(idx)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    lowered = None
+    for i in range(reps + 2):
+        lab.copy_(base)
+        if i >= 2:
+            ev[i - 2][0].record(stream)
+        lowered = contour.merge_min(peer, lab, stream=stream)
+        if i >= 2:
+            ev[i - 2][1].record(stream)
+    torch.cuda.synchronize()
+    ms = [a.elapsed_time(b) for a, b in ev]
+    med = statistics.median(ms)
+    gbps = 12.0 * n / (med / 1e3) / 1e9
+    return {"n": n, "ms_median": round(med, 4), "ms_min": round(min(ms), 4),
+            "lowered": int(lowered.item()), "exact": bool(torch.equal(lab, torch.minimum(base, peer))),
+            "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": "k_merge_min",
+                         "bytes_per_label": 12}}
+
+
 def gather_ceilings(contour, torch, s, d, n, sweep_ms):
     """The sweep's memory access pattern without its arithmetic
     (contour_gather_ceiling) on the copy the default solve sweeps: edges
@@ -678,6 +707,8 @@ def main():
                  ("hostloop_plain", dict(driver="hostloop")),
                  ("hostloop_atomic", dict(driver="hostloop", write="atomic"))])
             torch.cuda.empty_cache()
+        log("extra: label merge of the edge-split design, n = 2^24")
+        extras["merge_min_n16777216"] = bench_merge(contour, torch)
         log("extra: ER n=65536 m=524288")
         extras["er65536_m524288"], _ = bench_plain_extra(contour, torch, "er65536_m524288", args.seed, 20,
                                                          [("order_2", dict()), ("order_1", dict(order=1))])

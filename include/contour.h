@@ -370,6 +370,26 @@ int contour_batch_plan_destroy(contour_plan_t plan);
 int contour_cc_batched(const contour_batch_t* batch, const contour_opts_t* opts,
                        contour_stream_t stream);
 
+/* -------------------------------------------------------- sharding ---- */
+/* contour_merge_min: labels_inout[i] = min(labels_inout[i], peer[i]) for
+ * every i in [0, n).  The combine step of an edge split of one graph over
+ * several devices (not in the paper): each device sweeps its share of the
+ * edges against a full copy of the labels, and the copies are merged by an
+ * elementwise minimum.  In the pointer-graph view of the labels (Section
+ * II-A) every label names a vertex of the same component at or below its own
+ * id; the minimum of two such states keeps that and never raises a label, so
+ * rounds of local solves and merges reach the unique fixed point, and a round
+ * in which no solve changed a label and no merge lowered one is the last.
+ *   peer          device int32[n], read
+ *   labels_inout  device int32[n], updated in place; may be peer itself, must
+ *                 not otherwise overlap it
+ *   lowered       NULL, or device int32: set to the number of labels the
+ *                 merge lowered
+ * Enqueued on `stream`.  Returns CONTOUR_OK, CONTOUR_EINVAL (n < 0, a NULL
+ * array with n > 0) or CONTOUR_EHIP. */
+int contour_merge_min(const int32_t* peer, int32_t* labels_inout, int32_t n, int32_t* lowered,
+                      contour_stream_t stream);
+
 /* ------------------------------------------------------- profiling ---- */
 /* contour_gather_ceiling: a measurement kernel, the memory access pattern of
  * a sweep without its arithmetic, for comparing a sweep's time with what the

@@ -192,6 +192,25 @@ def group_edges(src, dst, n: int, stream=None, ranges: bool = False):
     return so, do
 
 
+def merge_min(peer, labels, stream=None, count: bool = True):
+    """contour_merge_min: labels = min(labels, peer) elementwise, in place
+    (stream ordered).  Returns a device int32 tensor of one element holding
+    the number of labels lowered, or None with count=False."""
+    torch = _torch()
+    for t in (peer, labels):
+        if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("peer and labels must be contiguous int32 CUDA tensors")
+    if peer.numel() != labels.numel():
+        raise ValueError("peer and labels must have the same length")
+    lowered = torch.empty(1, dtype=torch.int32, device=labels.device) if count else None
+    rc = load().contour_merge_min(ctypes.c_void_p(peer.data_ptr()), ctypes.c_void_p(labels.data_ptr()),
+                                  labels.numel(), ctypes.c_void_p(lowered.data_ptr() if count else 0),
+                                  _stream_ptr(stream))
+    if rc != OK:
+        raise ContourError(rc, "contour_merge_min")
+    return lowered
+
+
 def add_edges(src, dst, n: int, labels, stream=None, stats: bool = True, **opts):
     """contour_cc_add_edges: `labels` (int32 CUDA tensor of n) holds the exact
     labels of a graph; after the call (stream ordered) it holds the labels of

@@ -24,6 +24,7 @@ SOURCES = [
     "contour_reorder.hip",
     "contour_serve.cpp",
     "contour_noalloc.hip",
+    "contour_merge.hip",
 ]
 
 HIPCC_FLAGS = [

@@ -121,5 +121,9 @@ def test_gather_ceiling_and_count_reads_argument_errors_without_touching_the_dev
     assert lib.contour_gather_ceiling(p, p, 5, p, 4, 3, p, None) == contour.EINVAL      # bad mode
     assert lib.contour_gather_ceiling(None, None, 5, p, 4, 1, p, None) == contour.EINVAL
     assert lib.contour_gather_ceiling(None, None, 0, None, 0, 0, p, None) == contour.OK
+    assert lib.contour_merge_min(p, p, -1, None, None) == contour.EINVAL
+    assert lib.contour_merge_min(None, p, 5, None, None) == contour.EINVAL
+    assert lib.contour_merge_min(p, None, 5, None, None) == contour.EINVAL
+    assert lib.contour_merge_min(None, None, 0, None, None) == contour.OK
     assert lib.contour_cc_count_reads(None, None, 0, 0, None, None, None, None, None) == contour.EINVAL
     assert lib.contour_cc_count_reads(None, None, -1, 4, None, None, None, p, None) == contour.EINVAL

@@ -4,7 +4,8 @@ The design splits the edge list over p GPUs, each holding the whole label
 array; every round each GPU solves its share starting from the current
 labels (a warm-started contour_cc_ex) and the p label arrays are combined by
 an elementwise minimum.  Here the p shares are solved one after the other on
-the same GPU and the minimum is taken with torch: the final labels must equal
+the same GPU and merged with contour_merge_min (checked against torch's
+elementwise minimum and its count of lowered labels): the final labels must equal
 the oracle's for the whole graph (tolerance 0), and the round count must
 match the CPU model (oracle/contour_model.sharded_rounds) run on the same
 shares, up to the asynchronous sweeps converging differently inside a round
@@ -44,7 +45,14 @@ def rounds_on_one_gpu(contour, src, dst, n, share, p, **opts):
             _, st = contour.cc_ex(ps, pd, n, labels=Li, warm_start=True, **opts)
             assert contour.read_stats(st).status == 0
             outs.append(Li)
-        Ln = torch.stack(outs).min(dim=0).values
+        Ln = outs[0].clone()
+        lowered = 0
+        for Li in outs[1:]:
+            expect = int((Li < Ln).sum())
+            cnt = contour.merge_min(Li, Ln)
+            assert int(cnt.item()) == expect
+            lowered += expect
+        assert torch.equal(Ln, torch.stack(outs).min(dim=0).values)
         # every round keeps L[x] <= x and never raises a label
         assert bool((Ln <= torch.arange(n, dtype=torch.int32, device="cuda")).all())
         assert bool((Ln <= L).all())
@@ -79,3 +87,47 @@ def test_sharded_rounds_small_graph_against_model(contour):
     model, model_rounds, _ = cm.sharded_rounds(src, dst, n, share, 3)
     assert np.array_equal(labels, model)
     assert np.array_equal(labels, oracle.uf_labels(src, dst, n))
+
+
+@pytest.mark.parametrize("n", [1, 3, 4, 5, 1000, (1 << 20) + 3])
+@pytest.mark.parametrize("offset", [0, 1])
+def test_merge_min_matches_elementwise_minimum(contour, n, offset):
+    # aligned arrays take four labels per load, offset ones the scalar path;
+    # both cover a ragged tail
+    g = torch.Generator().manual_seed(n * 2 + offset)
+    a = torch.randint(0, max(n, 2), (n + offset,), generator=g, dtype=torch.int32).cuda()
+    b = torch.randint(0, max(n, 2), (n + offset,), generator=g, dtype=torch.int32).cuda()
+    peer, lab = a[offset:], b[offset:]
+    want = torch.minimum(peer, lab)
+    expect = int((peer < lab).sum())
+    before = b[:offset].clone()
+    print("merge_min n", n, "offset", offset, flush=True)
+    cnt = contour.merge_min(peer, lab)
+    torch.cuda.synchronize()
+    assert torch.equal(lab, want)
+    assert int(cnt.item()) == expect
+    assert torch.equal(b[:offset], before)  # nothing before the view is touched
+    # a second merge of the same peer changes nothing; merging with itself neither
+    assert int(contour.merge_min(peer, lab).item()) == 0
+    assert int(contour.merge_min(lab, lab).item()) == 0
+    assert torch.equal(lab, want)
+
+
+def test_merge_min_of_two_label_states_at_full_size(contour):
+    # two valid states of the R-MAT scale-24 label array (labels at or below
+    # their ids): the merge is their elementwise minimum, and merging the
+    # result into either one again lowers nothing
+    n = 1 << 24
+    idx = torch.arange(n, dtype=torch.int32, device="cuda")
+    g = torch.Generator(device="cuda").manual_seed(3)
+    la = (idx - torch.randint(0, 64, (n,), device="cuda", generator=g, dtype=torch.int32)).clamp_min(0)
+    lb = (idx - torch.randint(0, 64, (n,), device="cuda", generator=g, dtype=torch.int32)).clamp_min(0)
+    want = torch.minimum(la, lb)
+    expect = int((lb < la).sum())
+    print("merge_min full size", n, flush=True)
+    cnt = contour.merge_min(lb, la)
+    assert torch.equal(la, want)
+    assert int(cnt.item()) == expect
+    assert bool((la <= idx).all())
+    assert int(contour.merge_min(lb, la).item()) == 0
+    assert contour.merge_min(lb, la, count=False) is None
