@@ -328,20 +328,23 @@ def bench_batched(contour, torch, seed, steps):
             plan.launch()
         t1.record(stream)
         torch.cuda.synchronize()
+        per_graph_sweeps = plan.stats[:, 1].cpu().numpy().astype(np.int64)
         res = (t0.elapsed_time(t1) / steps, plan.labels.cpu().numpy(), plan.classes(),
-               plan.stats[:, 1].float().mean().item())
+               float(per_graph_sweeps.mean()), per_graph_sweeps)
         plan.close()
         return res
 
-    ms_default, batched_labels, classes, sweeps = run_plan(None)
+    ms_default, batched_labels, classes, sweeps, gsweeps = run_plan(None)
     table = os.path.join(ROOT, "paper_2311_02811_amd", "tuning_gfx950.json")
     ms_tuned = None
     tuned_exact = True
     if os.path.exists(table):
         from paper_2311_02811_amd import autotune
-        ms_tuned, tuned_labels, _, _ = run_plan(autotune.load_tuning(table))
+        ms_tuned, tuned_labels, _, sweeps_tuned, gsweeps_tuned = run_plan(autotune.load_tuning(table))
         tuned_exact = bool(np.array_equal(tuned_labels, exact))
     ms = min(ms_default, ms_tuned) if ms_tuned else ms_default
+    if ms_tuned and ms_tuned <= ms_default:
+        sweeps, gsweeps = sweeps_tuned, gsweeps_tuned
     # baseline: one contour_cc per graph, same device-resident data, on a
     # side stream, captured once and replayed
     labels = torch.empty(int(b.vertex_off[-1]), dtype=torch.int32, device="cuda")
@@ -379,7 +382,18 @@ def bench_batched(contour, torch, seed, steps):
     ms_base = a.elapsed_time(z)
     del graph
     G, M = b.num_graphs, int(b.m.sum())
-    return {"graphs": G, "sum_n": int(b.n.sum()), "sum_m": M, "classes": classes,
+    # roofline of the launch: edge-sweeps of every graph (its own sweep
+    # count times its edges) at the order-2 count of 24 bytes each (a lower
+    # bound where a class runs order 3 or chase-to-root), and the edge stream
+    # alone (8 bytes per edge-sweep); the small graphs' labels sit in LDS or
+    # the caches, so this is an algorithmic rate, not DRAM traffic
+    edge_sweeps = int((gsweeps * b.m.astype(np.int64)).sum())
+    alg = edge_sweeps * 24.0 / (ms / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(alg, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(alg / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": "batched plan launch",
+            "bytes_per_edge_sweep": 24, "edge_sweeps_per_launch": edge_sweeps,
+            "edge_stream_GBps": round(edge_sweeps * 8.0 / (ms / 1e3) / 1e9, 1)}
+    return {"graphs": G, "sum_n": int(b.n.sum()), "sum_m": M, "classes": classes, "roofline": roof,
             "ms_per_batch": round(ms, 3), "ms_per_batch_default": round(ms_default, 3),
             "ms_per_batch_tuned": round(ms_tuned, 3) if ms_tuned else None,
             "graphs_per_s": round(G / ms * 1e3, 1), "edges_per_s": round(M / ms * 1e3, 1),
