@@ -279,11 +279,11 @@ __device__ __forceinline__ void stage_window(int* w, const int* g, unsigned cnt)
     }
 }
 
-// Write the labels of window w that a store lowered (untagged) back to global memory
-// (g = labels + lo, buffer resource rsrc over the labels, byte offset of g
-// in it goff).  Plain mode writes through to memory (sc1 stores: 16 bytes for
-// four dirty labels in a row, else 4 bytes each), atomic mode takes the
-// atomic minimum of every dirty label (see persistent_solve).  Each thread
+// Write the labels of window w that a store lowered (untagged ones) back to
+// global memory (g = labels + lo, buffer resource rsrc over the labels, byte
+// offset of g in it goff).  Plain mode writes through to memory (sc1 stores: 16 bytes for
+// four lowered labels in a row, else 4 bytes each), atomic mode takes the
+// atomic minimum of every lowered label (see persistent_solve).  Each thread
 // handles four consecutive labels per step (one 16-byte LDS read; the
 // window's LDS holds a multiple of 32 labels, so the read stays inside it)
 // and kStageUnroll steps at a time.
