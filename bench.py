@@ -587,6 +587,9 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--edges-per-thread", type=int, default=0)
     ap.add_argument("--chunk-tiles", type=int, default=0)
+    ap.add_argument("--max-sweeps", type=int, default=0,
+                    help="stop each solve after this many sweeps (0: run to convergence); for profiling "
+                         "the first sweeps on their own, the labels are then not final")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads, batched, serving, cold and A/B measurements")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
@@ -623,7 +626,7 @@ def main():
     dr = int(args.dst_ranges) if args.dst_ranges.isdigit() else args.dst_ranges
     opts = dict(order=order, write=args.write, driver=args.driver, reorder=args.reorder,
                 block=args.block, edges_per_thread=args.edges_per_thread,
-                chunk_tiles=args.chunk_tiles, dst_ranges=dr)
+                chunk_tiles=args.chunk_tiles, dst_ranges=dr, max_sweeps=args.max_sweeps)
     s = torch.from_numpy(src).cuda()
     d = torch.from_numpy(dst).cuda()
     log("timing %d steps after %d warm-up steps: n=%d m=%d %r" % (args.steps, args.warmup, n, m, opts))
@@ -633,7 +636,8 @@ def main():
     status = sorted(set(x[0] for x in r["stats"]))
     value = m / (ms_per_step / 1e3)
     default_cfg = (args.reorder, args.block, args.edges_per_thread, args.chunk_tiles, args.write,
-                   args.driver, args.order, args.dst_ranges) == ("auto", 0, 0, 0, "plain", "persistent", "2", "auto")
+                   args.driver, args.order, args.dst_ranges, args.max_sweeps) == (
+                       "auto", 0, 0, 0, "plain", "persistent", "2", "auto", 0)
     roof = roofline(order, m, r, profile_figures(args.workload) if default_cfg else None, n)
     out = {
         "metric": METRIC,
@@ -653,7 +657,8 @@ def main():
         "config": {"workload": args.workload, "n": n, "m": m, "seed": args.seed,
                    "order": order, "write": args.write, "driver": args.driver,
                    "reorder": args.reorder, "dst_ranges": args.dst_ranges, "block": args.block,
-                   "edges_per_thread": args.edges_per_thread, "chunk_tiles": args.chunk_tiles},
+                   "edges_per_thread": args.edges_per_thread, "chunk_tiles": args.chunk_tiles,
+                   "max_sweeps": args.max_sweeps},
         "sweeps": {"min": min(sweeps), "max": max(sweeps), "mean": statistics.mean(sweeps)},
         "status": status,
         "edge_sweeps_per_s": round(statistics.mean(sweeps) * m / (statistics.mean(r["kernel_ms"]) / 1e3), 1),
