@@ -227,6 +227,32 @@ def test_edge_cases(contour):
     assert np.array_equal(got, exp)
 
 
+@pytest.mark.parametrize("mode", [dict(reorder="on"), dict(reorder="on", write="atomic"),
+                                  dict(reorder="on", order="full"), dict(reorder="off")],
+                         ids=["window", "window-atomic", "window-full", "flat"])
+def test_ids_at_the_top_of_the_window_range(contour, mode):
+    # label windows are used up to n = 2^30 - 1 and tag staged labels with
+    # bit 30: a graph on ids at the start of the last source block (blocks of
+    # 2^20 ids here, so a task's window covers them), everything else
+    # isolated
+    n = (1 << 30) - 1
+    k = 6000
+    lo = 1023 << 20
+    src, dst = graphgen.er(k, 9000, 41)
+    exp = oracle.uf_labels(src, dst, k) + lo
+    s, d = dev(src.astype(np.int64) + lo), dev(dst.astype(np.int64) + lo)
+    banner("top ids %r" % (mode,))
+    labels, st = contour.cc_ex(s, d, n, **mode)
+    torch.cuda.synchronize()
+    assert contour.read_stats(st).status == 0
+    assert np.array_equal(labels[lo:lo + k].cpu().numpy(), exp)
+    # everything below is isolated: its own label
+    assert bool((labels[:lo] == torch.arange(lo, dtype=torch.int32, device="cuda")).all())
+    assert bool((labels[lo + k:] == torch.arange(lo + k, n, dtype=torch.int32, device="cuda")).all())
+    del labels
+    torch.cuda.empty_cache()
+
+
 def test_reorder_leaves_inputs_untouched(contour):
     src, dst = graphgen.rmat(16, 8, 3)
     n = 1 << 16
